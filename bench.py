@@ -1,0 +1,173 @@
+"""Benchmark: binary64 arguments checked per second on the 2^40-argument exp
+slice (exp on [1, 1 + 2^-12), round-to-nearest, eps = 2^-32 ulp; 4096
+sub-intervals of 2^28 arguments, degree-4 Taylor tables at 256 bits, degree-1
+pieces of N = 2^18).
+
+One step is one pass of the whole hot path over the slice with the initial
+tables already resident in HBM: tabulation of the 2^22 pieces, degree-1
+search of every piece, exact recheck of every candidate, and the result list
+copied back to the host.  The fused form (one launch) is the timed step; the
+plain launch chain (tabulate -> search -> recheck) is timed beside it.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "binary64 args checked/sec (exp, 2^40 slice); batched vs plain speedup, p99"
+PEAK_INT32_OPS = 256 * 64 * 2.4e9     # 256 CUs x 64 lanes x 2.4 GHz, one op/lane/clock
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-plain", action="store_true")
+    p.add_argument("--cpu-subs", type=int, default=16,
+                   help="sub-intervals in the oracle's timed sample")
+    return p.parse_args()
+
+
+def ops_model(spec, pieces, cand, quotients):
+    """Algorithmic int32 VALU operations of one pass:
+    tabulation: one 32-bit limb add per limb of each difference-row update,
+    sum_j (delta - j) W/32 per piece; search: 96 ops per partial quotient of
+    the exact closest-point walk plus 12 per candidate step; recheck: each
+    candidate multiplies delta words by a 128-bit binomial (W/32 x 4 limb
+    products truncated to W bits, 2 ops each) and adds them."""
+    L = spec.W // 32
+    tab = sum(spec.delta - j for j in range(spec.delta + 1)) * L
+    mul = 2 * sum(max(L - j, 0) for j in range(4))
+    rechk = spec.delta * (mul + L) + 12
+    return pieces * tab + quotients * 96 + cand * rechk
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); every "
+              "box in this setup has a single MI355X", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1211_3056_amd import _lib, api, pipeline
+    from paper_1211_3056_amd.prep import JobSpec, prepare
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    spec = JobSpec(**synth.CONFIG3)
+    t0 = time.time()
+    P = prepare(spec)
+    prep_s = time.time() - t0
+    table, win, thr = pipeline.upload(P)
+    ctx = api.context()
+    dev = table.device
+    stream = torch.cuda.current_stream()
+    cap = 1 << 16
+    out = torch.empty(cap * _lib.RESULT_BYTES, dtype=torch.uint8, device=dev)
+    count = torch.zeros(1, dtype=torch.uint64, device=dev)
+    stats = torch.zeros(4, dtype=torch.uint64, device=dev)
+    count_h = torch.zeros(1, dtype=torch.uint64).pin_memory()
+    res_h = torch.zeros(cap * _lib.RESULT_BYTES, dtype=torch.uint8).pin_memory()
+    n_sub = spec.n_sub
+
+    def step(ev=None):
+        count.zero_()
+        stats.zero_()
+        if ev:
+            ev[0].record(stream)
+        _lib.hr_pipeline(ctx, table, n_sub, spec.delta, spec.tau, spec.W, spec.N, win, thr, out,
+                         cap, count, stats, stream)
+        if ev:
+            ev[1].record(stream)
+        count_h.copy_(count, non_blocking=True)
+        res_h.copy_(out, non_blocking=True)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(evs[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = [a.elapsed_time(b) for a, b in evs]
+    n_res = int(count_h.numpy()[0])
+    assert n_res <= cap
+    st = stats.cpu().numpy()
+    pieces, cand, quot = int(st[0]), int(st[1]), int(st[3])
+    res = res_h[: n_res * _lib.RESULT_BYTES].numpy().view(api.RESULT_DTYPE)
+    hr_cases = int((res["cls"] == 1).sum())
+    undecided = int((res["cls"] == 2).sum())
+    ms_per_step = wall * 1000 / args.steps
+    args_total = spec.count
+    value = args_total / (ms_per_step / 1000)
+    kern_avg = sum(kern_ms) / len(kern_ms)
+    ops = ops_model(spec, pieces, cand, quot)
+    achieved = ops / (kern_avg / 1000) / 1e12
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "args/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "exp_rn_slice_2^40_[1,1+2^-12)_eps2^-32_N2^18_tau2^10_deg4_W256",
+                   "form": "fused", "sub_intervals": n_sub, "pieces": pieces},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_INT32_OPS / 1e12,
+                     "unit": "Tops/s (int32 VALU, algorithmic)",
+                     "frac": achieved / (PEAK_INT32_OPS / 1e12), "traffic": None,
+                     "kernel": "k_pipeline<8,4>", "kernel_ms": kern_avg},
+        "hr_cases": hr_cases, "undecided": undecided, "candidates": cand,
+        "partial_quotients": quot, "host_prep_s": prep_s,
+        "end_to_end_args_per_s": args_total / (prep_s + ms_per_step / 1000),
+    }
+    if not args.no_plain:
+        tp = []
+        for i in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            hr_plain, pst = pipeline.run_plain(P, (table, win, thr), ctx=ctx)
+            torch.cuda.synchronize()
+            tp.append(time.perf_counter() - t0)
+        line["plain_form"] = {"ms_per_step": min(tp) * 1000,
+                              "value": args_total / min(tp), "candidates": pst["candidates"],
+                              "hr_cases": len(hr_plain)}
+    if not args.no_cpu_baseline:
+        from oracle import hr as ohr
+        from oracle import native
+        from oracle.taylor import Job
+        job = Job(**synth.CONFIG3)
+        subs = list(range(0, n_sub, max(1, n_sub // args.cpu_subs)))[: args.cpu_subs]
+        t0 = time.perf_counter()
+        ohr.pipeline(job, subs=subs)
+        cpu_s = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": len(subs) * spec.per_sub / cpu_s, "unit": "args/s",
+                                "cores": native.threads_default(), "kind": "oracle",
+                                "sample": f"{len(subs)} of {n_sub} sub-intervals "
+                                          f"({len(subs) * spec.per_sub} args), {cpu_s:.1f} s"}
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,178 @@
+/*
+ * hrsearch: hard-to-round (HR) case search on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the hot path of Lefevre's HR-case search as restated by Fortin,
+ * Gouicem and Graillat, "GPU-accelerated generation of correctly-rounded
+ * elementary functions": the tabulation of fixed-point polynomial pieces
+ * (Sec. 5 of the paper) and the degree-1 search of every k with
+ * (b - k a) mod 1 below a threshold (Sec. 3.1, Eq. 1; Sec. 4).
+ *
+ * Conventions shared by every entry point
+ *  - Every array argument is a DEVICE pointer on the context's device unless
+ *    stated otherwise; `stream` is a hipStream_t (NULL = default stream).
+ *    All calls are asynchronous on that stream: outputs are valid after the
+ *    stream is synchronised.
+ *  - The caller owns every buffer.  The library never frees caller memory;
+ *    it allocates only the context's internal scratch (hr_create and,
+ *    growing, inside calls that need more).
+ *  - Errors are status codes; nothing is thrown across the ABI.  HR_EINVAL is
+ *    returned before any launch for invalid sizes or null pointers; device
+ *    errors of a launch are returned as HR_EDEVICE.
+ *  - Fixed point: a fraction in [0, 1) is stored as an unsigned integer
+ *    value * 2^W (W = 64 for a, b and windows).  Arithmetic is mod 1, i.e.
+ *    wrap-around.  A W-bit word (W in {128, 192, 256}) is W/64 uint64 limbs,
+ *    least significant limb first.
+ *  - Identical inputs give identical output bytes (no atomics decide data
+ *    placement, except in hr_pipeline whose result set is sorted by the
+ *    caller; its order on the device is unspecified).
+ *  - One context per host thread; calls on one context are not reentrant.
+ */
+#ifndef HRSEARCH_H
+#define HRSEARCH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HR_ABI_VERSION 1
+#define HR_MAX_DEGREE 6
+
+typedef struct hr_ctx hr_ctx;
+
+typedef enum {
+    HR_OK = 0,
+    HR_EINVAL = -1,      /* invalid argument; nothing launched            */
+    HR_ECAPACITY = -2,   /* an output buffer was too small (see callers)  */
+    HR_EDEVICE = -3,     /* HIP runtime or launch error                   */
+    HR_ENOMEM = -4       /* device scratch allocation failed              */
+} hr_status;
+
+/* ABI version of the loaded library (HR_ABI_VERSION). */
+int hr_abi_version(void);
+
+/* Static text for a status code. */
+const char* hr_status_str(int status);
+
+/* Create a context on HIP device `device`.  *out receives the context.
+ * Returns HR_EINVAL for a null `out` or a bad device index. */
+hr_status hr_create(hr_ctx** out, int device);
+
+/* Release a context and its scratch.  NULL is accepted. */
+hr_status hr_destroy(hr_ctx* ctx);
+
+/*
+ * hr_search -- degree-1 search (Sec. 3.1 Eq. 1 of the paper, computing the
+ * whole set behind the minimum that Alg. 1-4 bound from below).
+ *
+ * For each instance i < n, with a window start lo and width d shared by the
+ * `group` consecutive instances i / group:
+ *     hits(i) = { k in [0, N[i]) : (b[i] - lo - k a[i]) mod 2^64 < d }.
+ *
+ *  a, b        uint64[n]   slope and offset of b - a x (fractions * 2^64)
+ *  N           uint32[n]   instance lengths (0 allowed: no hits)
+ *  win_lo      uint64[ceil(n/group)] window starts (NULL: all zero)
+ *  win_d       uint64[ceil(n/group)] window widths (hit iff distance < d)
+ *  group       instances per window entry (>= 1)
+ *  counts      uint32[n]   out: number of hits of each instance
+ *  offsets     uint64[n]   out: exclusive prefix sum of counts
+ *  hits        uint32[cap] out: k values, CSR by instance: the hits of
+ *              instance i are hits[offsets[i] .. offsets[i] + counts[i]),
+ *              ordered by increasing distance (b - lo - k a) mod 2^64, ties
+ *              (repeated points, periodic a) by increasing k.
+ *  hit_inst    uint32[cap] out (may be NULL): instance index of each hit
+ *  cap         capacity of hits / hit_inst (entries); hits at positions
+ *              >= cap are not written
+ *  total       uint64[1]   out: total number of hits (may exceed cap: the
+ *              caller checks *total <= cap after synchronising and retries
+ *              with a larger buffer otherwise)
+ * Errors: HR_EINVAL for n > 2^32 - 1, group == 0, or a null required pointer.
+ */
+hr_status hr_search(hr_ctx* ctx, const uint64_t* a, const uint64_t* b, const uint32_t* N,
+                    uint64_t n, const uint64_t* win_lo, const uint64_t* win_d, uint32_t group,
+                    uint32_t* counts, uint64_t* offsets, uint32_t* hits, uint32_t* hit_inst,
+                    uint64_t cap, uint64_t* total, void* stream);
+
+/*
+ * hr_tabulate -- tabulation of degree-1 pieces (Sec. 5 of the paper:
+ * hierarchical method, straightforward shift for packet starts, tabulated
+ * difference shift inside packets).
+ *
+ * Sub-interval s holds its polynomial as the initial table
+ *     T_s[j][l] = Delta_N^l Delta_1^j R_s(0),  j + l <= degree,
+ * so that piece i of s has r_j(i) = sum_l T_s[j][l] C(i, l) mod 1 and the
+ * piece polynomial P_i(x) = sum_j r_j(i) C(x, j).
+ *
+ *  table       uint64[n_sub * E * L], E = (degree+1)(degree+2)/2,
+ *              L = width_bits/64: entry (j, l) of sub-interval s is the
+ *              W-bit word at limbs [(s*E + e(j,l))*L, +L), e(j, l) =
+ *              sum_{j'<j} (degree - j' + 1) + l (rows j, then l)
+ *  n_sub, degree (1..HR_MAX_DEGREE), tau (pieces per sub-interval, >= 1),
+ *  width_bits  in {128, 192, 256}
+ *  a_out,b_out uint64[n_sub * tau] out, piece (s, i) at s*tau + i:
+ *              b = floor(2^64 frac(r_0(i))), a = floor(2^64 frac(-r_1(i)))
+ * Errors: HR_EINVAL for bad width/degree, tau == 0, tau^degree >= 2^128,
+ * or null pointers.
+ */
+hr_status hr_tabulate(hr_ctx* ctx, const uint64_t* table, uint32_t n_sub, uint32_t degree,
+                      uint32_t tau, uint32_t width_bits, uint64_t* a_out, uint64_t* b_out,
+                      void* stream);
+
+/*
+ * hr_recheck -- exact evaluation of candidates (the paper's phase 3 test,
+ * Sec. 4.1, applied to the candidates of the degree-1 search).
+ *
+ * For candidate c, piece inst = cand_inst[c] (sub-interval s = inst / tau,
+ * piece i = inst % tau) and argument offset k = cand_k[c]:
+ *     V = P_i(k) = sum_j r_j(i) C(k, j) mod 2^W  (table as in hr_tabulate)
+ * value_out[c] = floor(V / 2^(W-64)) (top 64 bits) and, with the four
+ * thresholds of sub-interval s, thr[4s..4s+3] = (hr_lo, hr_hi, rej_lo, rej_hi):
+ *     class_out[c] = 1 if hr_lo <= t <= hr_hi          (HR case for sure)
+ *                    0 if rej_lo <= t <= rej_hi        (not an HR case)
+ *                    2 otherwise                       (undecided)
+ *                    255 if cand_inst[c] >= n_sub * tau  (value_out[c] = 0)
+ *  k must satisfy k^degree < 2^128 (checked through max_k).
+ * Errors: HR_EINVAL as for hr_tabulate, or max_k^degree >= 2^128.
+ */
+hr_status hr_recheck(hr_ctx* ctx, const uint64_t* table, uint32_t n_sub, uint32_t degree,
+                     uint32_t tau, uint32_t width_bits, const uint32_t* cand_inst,
+                     const uint32_t* cand_k, uint64_t n_cand, uint32_t max_k,
+                     const uint64_t* thr, uint64_t* value_out, uint8_t* class_out,
+                     void* stream);
+
+/* One result of hr_pipeline: an argument whose piece value passed the
+ * exact test (cls 1) or fell inside the error margin (cls 2, to be decided
+ * by the caller at higher precision). */
+typedef struct {
+    uint32_t sub;      /* sub-interval                                  */
+    uint32_t piece;    /* piece inside the sub-interval                  */
+    uint32_t k;        /* argument offset inside the piece               */
+    uint32_t cls;      /* 1 = HR case, 2 = undecided                     */
+    uint64_t value;    /* top 64 bits of P_piece(k) mod 1                */
+} hr_result;
+
+/*
+ * hr_pipeline -- fused tabulate + search + recheck of whole sub-intervals in
+ * one launch (one pass of the hot path; no (a, b) or candidate lists in HBM).
+ *
+ * Same table and thresholds as hr_tabulate / hr_recheck.  Every piece of
+ * every sub-interval has N arguments.  win[2s], win[2s+1] = (lo, d) is the
+ * degree-1 window of sub-interval s: candidates are the k < N with
+ * (b - lo - k a) mod 2^64 < d, as in hr_search.  Each candidate is evaluated
+ * exactly and classified; results of class 1 and 2 are appended to `out`
+ * (capacity cap entries, order unspecified); *count (device) receives their
+ * number (may exceed cap).  stats (device, uint64[4], may be NULL) is
+ * incremented by: pieces, candidates, results, partial quotients.
+ * Errors: as hr_tabulate / hr_recheck, N == 0, or N^degree >= 2^128.
+ */
+hr_status hr_pipeline(hr_ctx* ctx, const uint64_t* table, uint32_t n_sub, uint32_t degree,
+                      uint32_t tau, uint32_t width_bits, uint32_t N, const uint64_t* win,
+                      const uint64_t* thr, hr_result* out, uint64_t cap, uint64_t* count,
+                      uint64_t* stats, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HRSEARCH_H */

@@ -1,0 +1,138 @@
+"""Thin ctypes binding of libhrsearch.so (include/hrsearch.h).
+
+Argument marshalling only: every entry point takes torch tensors (device
+memory) and passes their data pointers and the current HIP stream to the C
+ABI.  There is no CPU fallback: if the library is missing, loading fails
+loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhrsearch.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "hrsearch.h")
+
+HR_OK, HR_EINVAL, HR_ECAPACITY, HR_EDEVICE, HR_ENOMEM = 0, -1, -2, -3, -4
+
+_lib = None
+
+
+class HRError(RuntimeError):
+    def __init__(self, fn, status):
+        super().__init__(f"{fn} failed: {status_str(status)} ({status})")
+        self.status = status
+
+
+class hr_result(ctypes.Structure):
+    _fields_ = [("sub", ctypes.c_uint32), ("piece", ctypes.c_uint32), ("k", ctypes.c_uint32),
+                ("cls", ctypes.c_uint32), ("value", ctypes.c_uint64)]
+
+
+RESULT_BYTES = ctypes.sizeof(hr_result)
+EXPORTS = ("hr_abi_version", "hr_status_str", "hr_create", "hr_destroy", "hr_search",
+           "hr_tabulate", "hr_recheck", "hr_pipeline")
+
+
+def lib():
+    """Load libhrsearch.so (built by __graft_entry__.build()); raise if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    P, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+    L.hr_abi_version.restype = i32
+    L.hr_abi_version.argtypes = []
+    L.hr_status_str.restype = ctypes.c_char_p
+    L.hr_status_str.argtypes = [i32]
+    L.hr_create.restype = i32
+    L.hr_create.argtypes = [ctypes.POINTER(P), i32]
+    L.hr_destroy.restype = i32
+    L.hr_destroy.argtypes = [P]
+    L.hr_search.restype = i32
+    L.hr_search.argtypes = [P, P, P, P, u64, P, P, u32, P, P, P, P, u64, P, P]
+    L.hr_tabulate.restype = i32
+    L.hr_tabulate.argtypes = [P, P, u32, u32, u32, u32, P, P, P]
+    L.hr_recheck.restype = i32
+    L.hr_recheck.argtypes = [P, P, u32, u32, u32, u32, P, P, u64, u32, P, P, P, P]
+    L.hr_pipeline.restype = i32
+    L.hr_pipeline.argtypes = [P, P, u32, u32, u32, u32, u32, P, P, P, u64, P, P, P]
+    _lib = L
+    return L
+
+
+def status_str(status: int) -> str:
+    return lib().hr_status_str(status).decode()
+
+
+def _check(fn, status):
+    if status != HR_OK:
+        raise HRError(fn, status)
+
+
+def _p(t):
+    """Data pointer of a tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """An hr_ctx on one device (hr_create / hr_destroy)."""
+
+    def __init__(self, device: int = 0):
+        self.device = device
+        h = ctypes.c_void_p()
+        _check("hr_create", lib().hr_create(ctypes.byref(h), device))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            lib().hr_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def hr_search(ctx, a, b, N, win_lo, win_d, group, counts, offsets, hits, hit_inst, cap, total,
+              stream=None):
+    _check("hr_search", lib().hr_search(ctx.handle, _p(a), _p(b), _p(N), a.numel(), _p(win_lo),
+                                        _p(win_d), group, _p(counts), _p(offsets), _p(hits),
+                                        _p(hit_inst), cap, _p(total), _stream(stream)))
+
+
+def hr_tabulate(ctx, table, n_sub, degree, tau, width, a_out, b_out, stream=None):
+    _check("hr_tabulate", lib().hr_tabulate(ctx.handle, _p(table), n_sub, degree, tau, width,
+                                            _p(a_out), _p(b_out), _stream(stream)))
+
+
+def hr_recheck(ctx, table, n_sub, degree, tau, width, cand_inst, cand_k, max_k, thr,
+               value_out, class_out, stream=None):
+    _check("hr_recheck", lib().hr_recheck(ctx.handle, _p(table), n_sub, degree, tau, width,
+                                          _p(cand_inst), _p(cand_k), cand_k.numel(), max_k,
+                                          _p(thr), _p(value_out), _p(class_out), _stream(stream)))
+
+
+def hr_pipeline(ctx, table, n_sub, degree, tau, width, N, win, thr, out, cap, count, stats,
+                stream=None):
+    _check("hr_pipeline", lib().hr_pipeline(ctx.handle, _p(table), n_sub, degree, tau, width, N,
+                                            _p(win), _p(thr), _p(out), cap, _p(count), _p(stats),
+                                            _stream(stream)))

@@ -1,0 +1,539 @@
+// HIP kernels and C ABI of the HR-case search (gfx950).
+//
+// Kernels
+//   k_search_count / k_scan_blocks / k_search_emit   degree-1 search, CSR out
+//   k_tabulate                                       pieces (a, b)
+//   k_recheck                                        exact candidate values
+//   k_pipeline                                       fused tabulate+search+recheck
+//
+// Every kernel maps one lane to one independent unit of work (an instance,
+// a packet of pieces, a candidate): the search is embarrassingly parallel
+// over sub-domains (Sec. 1.2 of the paper).  Nothing here is a dense
+// contraction; all arithmetic is 32/64-bit integer VALU work plus one f64
+// division per quotient estimate.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <stdlib.h>
+
+#include "../../include/hrsearch.h"
+#include "hr_core.h"
+
+struct hr_ctx {
+    int device;
+    void* scratch;
+    size_t scratch_bytes;
+};
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / 64;
+
+// ---------------------------------------------------------------- scans
+
+__device__ uint64_t wave_incl_scan(uint64_t v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint64_t t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+__device__ uint64_t wave_sum(uint64_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Exclusive scan over a block of kBlock lanes; *total receives the sum.
+__device__ uint64_t block_excl_scan(uint64_t v, uint64_t* total) {
+    __shared__ uint64_t wsum[kWaves];
+    const uint64_t inc = wave_incl_scan(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 63) wsum[w] = inc;
+    __syncthreads();
+    uint64_t base = 0, tot = 0;
+#pragma unroll
+    for (int j = 0; j < kWaves; ++j) {
+        if (j < w) base += wsum[j];
+        tot += wsum[j];
+    }
+    __syncthreads();
+    *total = tot;
+    return base + inc - v;
+}
+
+// ---------------------------------------------------------------- search
+
+__global__ __launch_bounds__(kBlock) void k_search_count(
+    const uint64_t* __restrict__ a, const uint64_t* __restrict__ b,
+    const uint32_t* __restrict__ N, uint64_t n, const uint64_t* __restrict__ lo,
+    const uint64_t* __restrict__ d, uint32_t group, uint32_t* __restrict__ counts,
+    uint64_t* __restrict__ block_sums) {
+    const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    uint64_t c = 0;
+    if (i < n) {
+        const uint64_t g = i / group;
+        const uint64_t bb = b[i] - (lo ? lo[g] : 0);
+        c = hr::search_each(a[i], bb, N[i], d[g], [](uint64_t) {});
+        counts[i] = (uint32_t)c;
+    }
+    uint64_t tot;
+    block_excl_scan(c, &tot);
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+}
+
+// Exclusive scan of nb block sums in place, by one workgroup; total[0] = sum.
+__global__ __launch_bounds__(kBlock) void k_scan_blocks(uint64_t* __restrict__ sums, uint64_t nb,
+                                                       uint64_t* __restrict__ total) {
+    uint64_t carry = 0;
+    for (uint64_t base = 0; base < nb; base += kBlock) {
+        const uint64_t i = base + threadIdx.x;
+        const uint64_t v = i < nb ? sums[i] : 0;
+        uint64_t tot;
+        const uint64_t ex = block_excl_scan(v, &tot);
+        if (i < nb) sums[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) total[0] = carry;
+}
+
+__global__ __launch_bounds__(kBlock) void k_search_emit(
+    const uint64_t* __restrict__ a, const uint64_t* __restrict__ b,
+    const uint32_t* __restrict__ N, uint64_t n, const uint64_t* __restrict__ lo,
+    const uint64_t* __restrict__ d, uint32_t group, const uint32_t* __restrict__ counts,
+    const uint64_t* __restrict__ block_off, uint64_t* __restrict__ offsets,
+    uint32_t* __restrict__ hits, uint32_t* __restrict__ hit_inst, uint64_t cap) {
+    const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    const uint64_t c = i < n ? counts[i] : 0;
+    uint64_t tot;
+    const uint64_t off = block_off[blockIdx.x] + block_excl_scan(c, &tot);
+    if (i >= n) return;
+    offsets[i] = off;
+    if (c == 0 || off >= cap) return;
+    const uint64_t g = i / group;
+    const uint64_t bb = b[i] - (lo ? lo[g] : 0);
+    uint64_t pos = off;
+    hr::search_each(a[i], bb, N[i], d[g], [&](uint64_t k) {
+        if (pos < cap) {
+            hits[pos] = (uint32_t)k;
+            if (hit_inst) hit_inst[pos] = (uint32_t)i;
+        }
+        ++pos;
+    });
+}
+
+// ---------------------------------------------------------------- words
+
+template <int L>
+__device__ __forceinline__ void load_word(const uint64_t* __restrict__ p, hr::Word<L>& w) {
+#pragma unroll
+    for (int i = 0; i < L / 2; ++i) {
+        const uint64_t v = p[i];
+        w.w[2 * i] = (uint32_t)v;
+        w.w[2 * i + 1] = (uint32_t)(v >> 32);
+    }
+}
+
+template <int L>
+__device__ __forceinline__ uint64_t top64(const hr::Word<L>& w) {
+    return ((uint64_t)w.w[L - 1] << 32) | w.w[L - 2];
+}
+
+// floor(2^64 frac(-v)) = -ceil(v / 2^(W-64)) mod 2^64
+template <int L>
+__device__ __forceinline__ uint64_t neg_top64(const hr::Word<L>& w) {
+    uint32_t low = 0;
+#pragma unroll
+    for (int i = 0; i < L - 2; ++i) low |= w.w[i];
+    return 0 - (top64(w) + (low != 0));
+}
+
+// acc += T * C(x, m)  (m = 0: plain add)
+template <int L>
+__device__ __forceinline__ void mac_binom(hr::Word<L>& acc, const hr::Word<L>& T, uint64_t x, int m) {
+    if (m == 0) {
+        hr::wadd(acc, T);
+    } else {
+        uint32_t c[4];
+        hr::split128(hr::binom128(x, m), c);
+        hr::wmac128(acc, T, c);
+    }
+}
+
+__host__ __device__ constexpr int n_entries(int deg) { return (deg + 1) * (deg + 2) / 2; }
+__host__ __device__ constexpr int entry(int deg, int j, int l) {
+    return j * (deg + 1) - j * (j - 1) / 2 + l;
+}
+
+// Difference vector of row j at piece i0: v[l] = Delta^l r_j(i0) =
+// sum_m T[j][l+m] C(i0, m)  (straightforward shift, Sec. 5.2).
+template <int L, int DEG>
+__device__ __forceinline__ void row_start(const uint64_t* __restrict__ T, int j, uint64_t i0,
+                                          hr::Word<L>* v) {
+#pragma unroll
+    for (int l = 0; l <= DEG - j; ++l) {
+        hr::wzero(v[l]);
+#pragma unroll
+        for (int m = 0; l + m <= DEG - j; ++m) {
+            hr::Word<L> t;
+            load_word<L>(T + (size_t)entry(DEG, j, l + m) * (L / 2), t);
+            mac_binom(v[l], t, i0, m);
+        }
+    }
+}
+
+// One tabulated-difference step of a difference vector of length len
+// (Fig. 7: Delta^l(i+1) = Delta^l(i) + Delta^{l+1}(i)).
+template <int L>
+__device__ __forceinline__ void row_step(hr::Word<L>* v, int len) {
+#pragma unroll
+    for (int l = 0; l + 1 < len; ++l) hr::wadd(v[l], v[l + 1]);
+}
+
+// ---------------------------------------------------------------- tabulate
+
+template <int L, int DEG>
+__global__ __launch_bounds__(kBlock) void k_tabulate(const uint64_t* __restrict__ table,
+                                                    uint32_t n_sub, uint32_t tau, uint32_t nu,
+                                                    uint64_t* __restrict__ a_out,
+                                                    uint64_t* __restrict__ b_out) {
+    const uint64_t gid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    const uint64_t per_sub = (tau + nu - 1) / nu;
+    if (gid >= (uint64_t)n_sub * per_sub) return;
+    const uint64_t sub = gid / per_sub;
+    const uint64_t i0 = (gid % per_sub) * nu;
+    const uint32_t cnt = (uint32_t)hr::umin(nu, tau - i0);
+    const uint64_t* T = table + sub * n_entries(DEG) * (L / 2);
+    hr::Word<L> v0[DEG + 1], v1[DEG];
+    row_start<L, DEG>(T, 0, i0, v0);
+    row_start<L, DEG>(T, 1, i0, v1);
+    const uint64_t base = sub * tau + i0;
+    for (uint32_t s = 0; s < cnt; ++s) {
+        b_out[base + s] = top64(v0[0]);
+        a_out[base + s] = neg_top64(v1[0]);
+        row_step(v0, DEG + 1);
+        row_step(v1, DEG);
+    }
+}
+
+// ---------------------------------------------------------------- recheck
+
+template <int L>
+__device__ __forceinline__ uint8_t classify(uint64_t t, const uint64_t* __restrict__ thr) {
+    if (t >= thr[0] && t <= thr[1]) return 1;
+    if (t >= thr[2] && t <= thr[3]) return 0;
+    return 2;
+}
+
+template <int L, int DEG>
+__global__ __launch_bounds__(kBlock) void k_recheck(const uint64_t* __restrict__ table,
+                                                   uint32_t n_sub, uint32_t tau,
+                                                   const uint32_t* __restrict__ cinst,
+                                                   const uint32_t* __restrict__ ck, uint64_t n_cand,
+                                                   const uint64_t* __restrict__ thr,
+                                                   uint64_t* __restrict__ value_out,
+                                                   uint8_t* __restrict__ class_out) {
+    const uint64_t c = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= n_cand) return;
+    const uint32_t inst = cinst[c];
+    const uint64_t k = ck[c];
+    if ((uint64_t)inst >= (uint64_t)n_sub * tau) {   // not a piece of this table
+        value_out[c] = 0;
+        class_out[c] = 255;
+        return;
+    }
+    const uint64_t sub = inst / tau, i = inst % tau;
+    const uint64_t* T = table + sub * n_entries(DEG) * (L / 2);
+    hr::Word<L> V;
+    hr::wzero(V);
+#pragma unroll
+    for (int j = 0; j <= DEG; ++j) {
+        hr::Word<L> r;
+        hr::wzero(r);
+#pragma unroll
+        for (int l = 0; l <= DEG - j; ++l) {
+            hr::Word<L> t;
+            load_word<L>(T + (size_t)entry(DEG, j, l) * (L / 2), t);
+            mac_binom(r, t, i, l);
+        }
+        mac_binom(V, r, k, j);
+    }
+    const uint64_t t = top64(V);
+    value_out[c] = t;
+    class_out[c] = classify<L>(t, thr + 4 * sub);
+}
+
+// ---------------------------------------------------------------- pipeline
+
+template <int L, int DEG>
+__global__ __launch_bounds__(kBlock) void k_pipeline(
+    const uint64_t* __restrict__ table, uint32_t n_sub, uint32_t tau, uint32_t nu, uint32_t N,
+    const uint64_t* __restrict__ win, const uint64_t* __restrict__ thr, hr_result* __restrict__ out,
+    uint64_t cap, unsigned long long* __restrict__ count, unsigned long long* __restrict__ stats) {
+    const uint64_t gid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    const uint64_t per_sub = (tau + nu - 1) / nu;
+    uint64_t n_pieces = 0, n_cand = 0, n_res = 0, n_steps = 0;
+    if (gid < (uint64_t)n_sub * per_sub) {
+        const uint64_t sub = gid / per_sub;
+        const uint64_t i0 = (gid % per_sub) * nu;
+        const uint32_t cnt = (uint32_t)hr::umin(nu, tau - i0);
+        const uint64_t* T = table + sub * n_entries(DEG) * (L / 2);
+        const uint64_t wlo = win[2 * sub], wd = win[2 * sub + 1];
+        const uint64_t* th = thr + 4 * sub;
+        // full difference table of every row at i0
+        hr::Word<L> v[n_entries(DEG)];
+#pragma unroll
+        for (int j = 0; j <= DEG; ++j) row_start<L, DEG>(T, j, i0, v + entry(DEG, j, 0));
+        for (uint32_t s = 0; s < cnt; ++s) {
+            const uint64_t piece = i0 + s;
+            const uint64_t bb = top64(v[entry(DEG, 0, 0)]) - wlo;
+            const uint64_t aa = neg_top64(v[entry(DEG, 1, 0)]);
+            ++n_pieces;
+            uint32_t steps = 0;
+            n_cand += hr::search_each(aa, bb, N, wd, [&](uint64_t k) {
+                hr::Word<L> V = v[entry(DEG, 0, 0)];
+#pragma unroll
+                for (int j = 1; j <= DEG; ++j) mac_binom(V, v[entry(DEG, j, 0)], k, j);
+                const uint64_t t = top64(V);
+                const uint8_t cls = classify<L>(t, th);
+                if (cls) {
+                    const unsigned long long pos = atomicAdd(count, 1ull);
+                    if (pos < cap) {
+                        hr_result r;
+                        r.sub = (uint32_t)sub;
+                        r.piece = (uint32_t)piece;
+                        r.k = (uint32_t)k;
+                        r.cls = cls;
+                        r.value = t;
+                        out[pos] = r;
+                    }
+                    ++n_res;
+                }
+            }, &steps);
+            n_steps += steps;
+#pragma unroll
+            for (int j = 0; j <= DEG; ++j) row_step(v + entry(DEG, j, 0), DEG - j + 1);
+        }
+    }
+    if (stats) {
+        n_pieces = wave_sum(n_pieces);
+        n_cand = wave_sum(n_cand);
+        n_res = wave_sum(n_res);
+        n_steps = wave_sum(n_steps);
+        if ((threadIdx.x & 63) == 0) {
+            atomicAdd(stats + 0, (unsigned long long)n_pieces);
+            atomicAdd(stats + 1, (unsigned long long)n_cand);
+            atomicAdd(stats + 2, (unsigned long long)n_res);
+            atomicAdd(stats + 3, (unsigned long long)n_steps);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- host side
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+hr_status launched() {
+    return hipGetLastError() == hipSuccess ? HR_OK : HR_EDEVICE;
+}
+
+hr_status ensure_scratch(hr_ctx* ctx, size_t bytes) {
+    if (ctx->scratch_bytes >= bytes) return HR_OK;
+    if (ctx->scratch) {
+        if (hipDeviceSynchronize() != hipSuccess) return HR_EDEVICE;
+        if (hipFree(ctx->scratch) != hipSuccess) return HR_EDEVICE;
+        ctx->scratch = nullptr;
+        ctx->scratch_bytes = 0;
+    }
+    size_t want = bytes < (1u << 20) ? (1u << 20) : bytes;
+    if (hipMalloc(&ctx->scratch, want) != hipSuccess) {
+        ctx->scratch = nullptr;
+        return HR_ENOMEM;
+    }
+    ctx->scratch_bytes = want;
+    return HR_OK;
+}
+
+// x^deg < 2^128 ?
+bool pow_fits128(uint64_t x, uint32_t deg) {
+    unsigned __int128 v = 1;
+    for (uint32_t i = 0; i < deg; ++i) {
+        if (x != 0 && v > (~(unsigned __int128)0) / x) return false;
+        v *= x;
+    }
+    return true;
+}
+
+bool valid_poly(uint32_t degree, uint32_t width_bits) {
+    return degree >= 1 && degree <= HR_MAX_DEGREE &&
+           (width_bits == 128 || width_bits == 192 || width_bits == 256);
+}
+
+// Packets per lane for tabulation: long enough to amortise the packet start
+// (straightforward shift), short enough to leave >= 4 lanes per CU slot.
+uint32_t pick_nu(uint64_t n_sub, uint32_t tau) {
+    uint32_t nu = 16;
+    while (nu > 1 && (uint64_t)n_sub * ((tau + nu - 1) / nu) < 256ull * 256 * 4) nu >>= 1;
+    return nu;
+}
+
+#define HR_DISPATCH(WB, DEG, KERNEL_CALL)                               \
+    do {                                                                \
+        switch ((WB) / 32 * 16 + (DEG)) {                               \
+            HR_CASE(4, 1, KERNEL_CALL) HR_CASE(4, 2, KERNEL_CALL)       \
+            HR_CASE(4, 3, KERNEL_CALL) HR_CASE(4, 4, KERNEL_CALL)       \
+            HR_CASE(4, 5, KERNEL_CALL) HR_CASE(4, 6, KERNEL_CALL)       \
+            HR_CASE(6, 1, KERNEL_CALL) HR_CASE(6, 2, KERNEL_CALL)       \
+            HR_CASE(6, 3, KERNEL_CALL) HR_CASE(6, 4, KERNEL_CALL)       \
+            HR_CASE(6, 5, KERNEL_CALL) HR_CASE(6, 6, KERNEL_CALL)       \
+            HR_CASE(8, 1, KERNEL_CALL) HR_CASE(8, 2, KERNEL_CALL)       \
+            HR_CASE(8, 3, KERNEL_CALL) HR_CASE(8, 4, KERNEL_CALL)       \
+            HR_CASE(8, 5, KERNEL_CALL) HR_CASE(8, 6, KERNEL_CALL)       \
+            default: return HR_EINVAL;                                  \
+        }                                                               \
+    } while (0)
+#define HR_CASE(LL, DD, KERNEL_CALL) \
+    case LL * 16 + DD: {             \
+        constexpr int L_ = LL;       \
+        constexpr int D_ = DD;       \
+        KERNEL_CALL;                 \
+        break;                       \
+    }
+
+}  // namespace
+
+extern "C" {
+
+int hr_abi_version(void) { return HR_ABI_VERSION; }
+
+const char* hr_status_str(int s) {
+    switch (s) {
+        case HR_OK: return "ok";
+        case HR_EINVAL: return "invalid argument";
+        case HR_ECAPACITY: return "output capacity exceeded";
+        case HR_EDEVICE: return "HIP device or launch error";
+        case HR_ENOMEM: return "device allocation failed";
+        default: return "unknown status";
+    }
+}
+
+hr_status hr_create(hr_ctx** out, int device) {
+    if (!out) return HR_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess) return HR_EDEVICE;
+    if (device < 0 || device >= n) return HR_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return HR_EDEVICE;
+    hr_ctx* c = (hr_ctx*)calloc(1, sizeof(hr_ctx));
+    if (!c) return HR_ENOMEM;
+    c->device = device;
+    *out = c;
+    return HR_OK;
+}
+
+hr_status hr_destroy(hr_ctx* ctx) {
+    if (!ctx) return HR_OK;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->scratch) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(ctx->scratch);
+    }
+    free(ctx);
+    return HR_OK;
+}
+
+hr_status hr_search(hr_ctx* ctx, const uint64_t* a, const uint64_t* b, const uint32_t* N,
+                    uint64_t n, const uint64_t* win_lo, const uint64_t* win_d, uint32_t group,
+                    uint32_t* counts, uint64_t* offsets, uint32_t* hits, uint32_t* hit_inst,
+                    uint64_t cap, uint64_t* total, void* stream) {
+    if (!ctx || !win_d || !total || group == 0) return HR_EINVAL;
+    if (n > 0xffffffffull) return HR_EINVAL;
+    if (n > 0 && (!a || !b || !N || !counts || !offsets)) return HR_EINVAL;
+    if (cap > 0 && !hits) return HR_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return HR_EDEVICE;
+    hipStream_t st = as_stream(stream);
+    const uint64_t nb = (n + kBlock - 1) / kBlock;
+    hr_status s = ensure_scratch(ctx, (nb + 1) * sizeof(uint64_t));
+    if (s != HR_OK) return s;
+    uint64_t* bsum = (uint64_t*)ctx->scratch;
+    if (nb > 0) {
+        k_search_count<<<dim3((uint32_t)nb), dim3(kBlock), 0, st>>>(a, b, N, n, win_lo, win_d,
+                                                                    group, counts, bsum);
+        if ((s = launched()) != HR_OK) return s;
+    }
+    k_scan_blocks<<<1, kBlock, 0, st>>>(bsum, nb, total);
+    if ((s = launched()) != HR_OK) return s;
+    if (nb > 0) {
+        k_search_emit<<<dim3((uint32_t)nb), dim3(kBlock), 0, st>>>(
+            a, b, N, n, win_lo, win_d, group, counts, bsum, offsets, hits, hit_inst, cap);
+        if ((s = launched()) != HR_OK) return s;
+    }
+    return HR_OK;
+}
+
+hr_status hr_tabulate(hr_ctx* ctx, const uint64_t* table, uint32_t n_sub, uint32_t degree,
+                      uint32_t tau, uint32_t width_bits, uint64_t* a_out, uint64_t* b_out,
+                      void* stream) {
+    if (!ctx || !valid_poly(degree, width_bits) || tau == 0) return HR_EINVAL;
+    if (!pow_fits128(tau, degree)) return HR_EINVAL;
+    if (n_sub == 0) return HR_OK;
+    if (!table || !a_out || !b_out) return HR_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return HR_EDEVICE;
+    hipStream_t st = as_stream(stream);
+    const uint32_t nu = pick_nu(n_sub, tau);
+    const uint64_t lanes = (uint64_t)n_sub * ((tau + nu - 1) / nu);
+    const uint64_t blocks = (lanes + kBlock - 1) / kBlock;
+    if (blocks > 0xffffffffull) return HR_EINVAL;
+    HR_DISPATCH(width_bits, degree,
+                (k_tabulate<L_, D_><<<dim3((uint32_t)blocks), dim3(kBlock), 0, st>>>(
+                    table, n_sub, tau, nu, a_out, b_out)));
+    return launched();
+}
+
+hr_status hr_recheck(hr_ctx* ctx, const uint64_t* table, uint32_t n_sub, uint32_t degree,
+                     uint32_t tau, uint32_t width_bits, const uint32_t* cand_inst,
+                     const uint32_t* cand_k, uint64_t n_cand, uint32_t max_k,
+                     const uint64_t* thr, uint64_t* value_out, uint8_t* class_out,
+                     void* stream) {
+    if (!ctx || !valid_poly(degree, width_bits) || tau == 0) return HR_EINVAL;
+    if (!pow_fits128(tau, degree) || !pow_fits128(max_k, degree)) return HR_EINVAL;
+    if (n_cand == 0) return HR_OK;
+    if (!table || !cand_inst || !cand_k || !thr || !value_out || !class_out || n_sub == 0)
+        return HR_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return HR_EDEVICE;
+    hipStream_t st = as_stream(stream);
+    const uint64_t blocks = (n_cand + kBlock - 1) / kBlock;
+    if (blocks > 0xffffffffull) return HR_EINVAL;
+    HR_DISPATCH(width_bits, degree,
+                (k_recheck<L_, D_><<<dim3((uint32_t)blocks), dim3(kBlock), 0, st>>>(
+                    table, n_sub, tau, cand_inst, cand_k, n_cand, thr, value_out, class_out)));
+    return launched();
+}
+
+hr_status hr_pipeline(hr_ctx* ctx, const uint64_t* table, uint32_t n_sub, uint32_t degree,
+                      uint32_t tau, uint32_t width_bits, uint32_t N, const uint64_t* win,
+                      const uint64_t* thr, hr_result* out, uint64_t cap, uint64_t* count,
+                      uint64_t* stats, void* stream) {
+    if (!ctx || !valid_poly(degree, width_bits) || tau == 0 || N == 0) return HR_EINVAL;
+    if (!pow_fits128(tau, degree) || !pow_fits128(N, degree)) return HR_EINVAL;
+    if (!count) return HR_EINVAL;
+    if (n_sub == 0) return HR_OK;
+    if (!table || !win || !thr || (cap > 0 && !out)) return HR_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return HR_EDEVICE;
+    hipStream_t st = as_stream(stream);
+    const uint32_t nu = pick_nu(n_sub, tau);
+    const uint64_t lanes = (uint64_t)n_sub * ((tau + nu - 1) / nu);
+    const uint64_t blocks = (lanes + kBlock - 1) / kBlock;
+    if (blocks > 0xffffffffull) return HR_EINVAL;
+    HR_DISPATCH(width_bits, degree,
+                (k_pipeline<L_, D_><<<dim3((uint32_t)blocks), dim3(kBlock), 0, st>>>(
+                    table, n_sub, tau, nu, N, win, thr, out, cap,
+                    (unsigned long long*)count, (unsigned long long*)stats)));
+    return launched();
+}
+
+}  // extern "C"

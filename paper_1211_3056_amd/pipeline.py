@@ -1,0 +1,68 @@
+"""End-to-end HR-case search of one job on the GPU.
+
+prepare (host tables, windows, thresholds) -> device: either the fused
+kernel (hr_pipeline, one launch) or the plain launch chain
+(hr_tabulate -> hr_search -> hr_recheck) -> host decision of the few
+undecided values -> sorted HR offsets m (argument X0 + m h).
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import api
+from .prep import JobSpec, Prepared, is_hr, prepare
+
+
+def upload(P: Prepared, device="cuda"):
+    table = api.to_dev(P.tables.reshape(-1), torch.uint64, device)
+    win = api.to_dev(P.win.reshape(-1), torch.uint64, device)
+    thr = api.to_dev(P.thr.reshape(-1), torch.uint64, device)
+    return table, win, thr
+
+
+def _finish(P: Prepared, subs_idx, piece, k, cls):
+    """Global offsets of certain HR cases plus host-decided undecided ones."""
+    spec = P.spec
+    base = P.subs[subs_idx].astype(np.int64) * spec.per_sub + piece.astype(np.int64) * spec.N
+    m = base + k.astype(np.int64)
+    out = [int(x) for x in m[cls == 1]]
+    undecided = [int(x) for x in m[cls == 2]]
+    out += [x for x in undecided if is_hr(spec, x, P.uf)]
+    return sorted(out), len(undecided)
+
+
+def run_fused(P: Prepared, dev_args=None, ctx=None):
+    spec = P.spec
+    table, win, thr = dev_args or upload(P)
+    res, stats = api.pipeline(table, len(P.subs), spec.delta, spec.tau, spec.W, spec.N, win, thr,
+                              ctx=ctx)
+    hr, n_und = _finish(P, res["sub"], res["piece"], res["k"], res["cls"])
+    stats["undecided"] = n_und
+    return hr, stats
+
+
+def run_plain(P: Prepared, dev_args=None, ctx=None):
+    spec = P.spec
+    table, win, thr = dev_args or upload(P)
+    n_sub = len(P.subs)
+    a, b = api.tabulate(table, n_sub, spec.delta, spec.tau, spec.W, ctx=ctx)
+    N = api.to_dev(np.full(n_sub * spec.tau, spec.N, np.uint32), torch.uint32, a.device)
+    lo = api.to_dev(P.win[:, 0], torch.uint64, a.device)
+    d = api.to_dev(P.win[:, 1], torch.uint64, a.device)
+    counts, offsets, hits, inst = api.search(a, b, N, d, lo=lo, group=spec.tau, with_inst=True,
+                                             ctx=ctx)
+    value, cls = api.recheck(table, n_sub, spec.delta, spec.tau, spec.W, inst, hits, spec.N - 1,
+                             thr, ctx=ctx)
+    cls_h = cls.cpu().numpy()
+    keep = cls_h != 0
+    inst_h = inst.cpu().numpy()[keep].astype(np.int64)
+    k_h = hits.cpu().numpy()[keep]
+    hr, n_und = _finish(P, inst_h // spec.tau, inst_h % spec.tau, k_h, cls_h[keep])
+    return hr, {"pieces": n_sub * spec.tau, "candidates": int(hits.numel()),
+                "results": int(keep.sum()), "undecided": n_und}
+
+
+def search_job(spec: JobSpec, form: str = "fused", subs=None, ctx=None):
+    P = prepare(spec, subs)
+    return (run_fused if form == "fused" else run_plain)(P, ctx=ctx)

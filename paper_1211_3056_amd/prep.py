@@ -1,0 +1,260 @@
+"""Host preparation of HR-case search jobs.
+
+A job searches the binary64 arguments X0 + m h, 0 <= m < count, of f for
+round-to-nearest (or directed) hard-to-round cases at distance below
+eps = 2^-s output ulps (Sec. 3.1 of the paper: change of variable to integer
+arguments, HR test {y - c + eps} < 2 eps with c = 1/2 for nearest, 0 for
+directed).  The range is cut into sub-intervals of tau * N arguments and
+each sub-interval into tau pieces of N (Sec. 5, hierarchical method).
+
+For every sub-interval this module produces what the device path consumes:
+
+* the initial table T[j][l] = Delta_N^l Delta_1^j R(0) (j + l <= delta) of the
+  degree-delta Taylor polynomial R of f(X_t + x h)/u_f - c + eps, rounded
+  once to W-bit fractions.  R is held by its monomial coefficients c_n as
+  fixed-point integers with guard bits; the table is their image under the
+  exact integer matrices K_n[j][l] = Delta_N^l Delta_1^j (x^n)(0);
+* the degree-1 window (lo, d): every argument whose value can pass the HR
+  test has (b - lo - k a) mod 2^64 < d.  It covers the truncation to degree
+  one (bounded through interval bounds on R's derivatives, one-sided when
+  their sign is fixed), the approximation and rounding errors, and the
+  64-bit truncation of a and b;
+* the thresholds (hr_lo, hr_hi, rej_lo, rej_hi) on the top 64 bits of an
+  exact piece value: certainly HR, certainly not, or undecided (decided
+  here at high precision by ``decide``).
+
+Transcendental values come from mpmath at W + guard + 64 bits.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+from math import comb
+
+import mpmath
+import numpy as np
+from mpmath import mpf
+
+M64 = 1 << 64
+FUNCTIONS = ("exp", "exp2", "log", "sin", "cos")
+
+
+@dataclass(frozen=True)
+class JobSpec:
+    fname: str
+    X0: float
+    count: int
+    s: int                 # eps = 2^-s output ulps
+    mode: str = "rn"       # "rn" or "dir"
+    N: int = 1 << 16
+    tau: int = 1 << 8
+    delta: int = 3
+    W: int = 192
+
+    @property
+    def per_sub(self) -> int:
+        return self.N * self.tau
+
+    @property
+    def n_sub(self) -> int:
+        if self.count % self.per_sub:
+            raise ValueError("count must be a multiple of N * tau")
+        return self.count // self.per_sub
+
+    @property
+    def limbs(self) -> int:
+        return self.W // 64
+
+    @property
+    def entries(self) -> int:
+        return (self.delta + 1) * (self.delta + 2) // 2
+
+
+def _ulp(x) -> mpf:
+    """ulp of a binary64 number with x = m 2^e, m in [1/2, 1): 2^(e-53)."""
+    _, e = mpmath.frexp(mpf(x))
+    return mpf(2) ** (e - 53)
+
+
+def _f(fname, X):
+    if fname == "exp":
+        return mpmath.exp(X)
+    if fname == "exp2":
+        return mpmath.power(2, X)
+    if fname == "log":
+        return mpmath.log(X)
+    if fname == "sin":
+        return mpmath.sin(X)
+    if fname == "cos":
+        return mpmath.cos(X)
+    raise ValueError(fname)
+
+
+def _taylor_coeffs(fname, X, n_max, h, uf):
+    """f^(n)(X) h^n / (n! u_f), n <= n_max, at the current precision."""
+    out = []
+    if fname == "exp":
+        e = mpmath.exp(X)
+        t = e / uf
+        for n in range(n_max + 1):
+            out.append(t)
+            t = t * h / (n + 1)
+        return out
+    if fname == "exp2":
+        e = mpmath.power(2, X)
+        l2 = mpmath.ln2
+        t = e / uf
+        for n in range(n_max + 1):
+            out.append(t)
+            t = t * l2 * h / (n + 1)
+        return out
+    if fname == "log":
+        out.append(mpmath.log(X) / uf)
+        for n in range(1, n_max + 1):
+            # log^(n)(X)/n! = (-1)^(n-1) / (n X^n)
+            out.append((-1) ** (n - 1) * (h / X) ** n / (n * uf))
+        return out
+    if fname in ("sin", "cos"):
+        s, c = mpmath.sin(X), mpmath.cos(X)
+        cyc = [s, c, -s, -c] if fname == "sin" else [c, -s, -c, s]
+        fact = mpf(1)
+        for n in range(n_max + 1):
+            if n:
+                fact *= n
+            out.append(cyc[n % 4] * h ** n / (fact * uf))
+        return out
+    raise ValueError(fname)
+
+
+def _deriv_bound(fname, X_lo, X_hi, n):
+    """max |f^(n)| on [X_lo, X_hi] from closed forms (monotone or bounded)."""
+    if fname == "exp":
+        return mpmath.exp(X_hi)
+    if fname == "exp2":
+        return mpmath.ln2 ** n * mpmath.power(2, X_hi)
+    if fname == "log":
+        return mpmath.factorial(n - 1) / X_lo ** n
+    return mpf(1)
+
+
+def _k_matrices(N: int, delta: int):
+    """K[n][(j, l)] = Delta_N^l Delta_1^j (x^n) at 0, exact integers."""
+    K = []
+    for n in range(delta + 1):
+        Kn = {}
+        for j in range(delta + 1):
+            for l in range(delta - j + 1):
+                acc = 0
+                for s in range(l + 1):
+                    for m in range(j + 1):
+                        sign = -1 if (l - s + j - m) & 1 else 1
+                        acc += sign * comb(l, s) * comb(j, m) * (s * N + m) ** n
+                Kn[(j, l)] = acc
+        K.append(Kn)
+    return K
+
+
+@dataclass
+class Prepared:
+    spec: JobSpec
+    subs: np.ndarray        # sub-interval indices covered, int64
+    tables: np.ndarray      # uint64 (n, E, L)
+    win: np.ndarray         # uint64 (n, 2): lo, d
+    thr: np.ndarray         # uint64 (n, 4): hr_lo, hr_hi, rej_lo, rej_hi
+    h: mpf
+    uf: mpf
+
+
+def output_ulp(spec: JobSpec) -> mpf:
+    with mpmath.workprec(128):
+        h = _ulp(spec.X0)
+        lo = _f(spec.fname, mpf(spec.X0))
+        hi = _f(spec.fname, mpf(spec.X0) + (spec.count - 1) * h)
+        e1, e2 = mpmath.frexp(lo)[1], mpmath.frexp(hi)[1]
+        if e1 != e2 or lo <= 0:
+            raise ValueError(f"{spec.fname} leaves its output binade on this range")
+        return mpf(2) ** (e1 - 53)
+
+
+def prepare(spec: JobSpec, subs=None) -> Prepared:
+    """Tables, windows and thresholds for the given sub-intervals (default all)."""
+    if spec.fname not in FUNCTIONS:
+        raise ValueError(spec.fname)
+    if spec.W not in (128, 192, 256) or not 1 <= spec.delta <= 6:
+        raise ValueError("unsupported width or degree")
+    subs = np.arange(spec.n_sub, dtype=np.int64) if subs is None else np.asarray(subs, np.int64)
+    d, W, N, tau, L = spec.delta, spec.W, spec.N, spec.tau, spec.limbs
+    K = _k_matrices(N, d)
+    kmax = max(abs(v) for Kn in K for v in Kn.values())
+    G = kmax.bit_length() + 96
+    prec = W + G + 64
+    pairs = [(j, l) for j in range(d + 1) for l in range(d - j + 1)]
+    tables = np.zeros((len(subs), len(pairs), L), np.uint64)
+    win = np.zeros((len(subs), 2), np.uint64)
+    thr = np.zeros((len(subs), 4), np.uint64)
+    uf = output_ulp(spec)
+    with mpmath.workprec(prec):
+        h = _ulp(spec.X0)
+        eps = mpf(2) ** (-spec.s)
+        offset = eps - (mpf(1) / 2 if spec.mode == "rn" else 0)
+        scale = mpf(2) ** (W + G)
+        M = spec.per_sub
+        e_round = mpf(2) ** (-W) * sum(comb(N - 1, j) for j in range(d + 1)) \
+            * sum(comb(tau - 1, l) for l in range(d + 1))
+        e_row = mpf(2) ** (-W - 1) * sum(comb(tau - 1, l) for l in range(d + 1))
+        for row, t in enumerate(subs):
+            Xt = mpf(spec.X0) + int(t) * M * h
+            c = _taylor_coeffs(spec.fname, Xt, d, h, uf)
+            c[0] += offset
+            C = [int(mpmath.nint(cn * scale)) for cn in c]
+            for e, (j, l) in enumerate(pairs):
+                v = sum(C[n] * K[n][(j, l)] for n in range(d + 1))
+                v = ((v + (1 << (G - 1))) >> G) & ((1 << W) - 1)
+                for li in range(L):
+                    tables[row, e, li] = (v >> (64 * li)) & (M64 - 1)
+            # error budget of this sub-interval
+            nA = d + 1
+            e_approx = _deriv_bound(spec.fname, Xt, Xt + M * h, nA) * (M * h) ** nA \
+                / (mpmath.factorial(nA) * uf) * mpf("1.01")
+            mu = e_approx + e_round
+            # r_j(i) = Delta^j R(i N) lies in the range of R^(j) on [0, M + d]
+            Y = mpf(M + d)
+            t_lo = t_hi = mpf(0)
+            for j in range(2, d + 1):
+                base = c[j] * mpmath.factorial(j)
+                lo_j = hi_j = base
+                for n in range(j + 1, d + 1):
+                    term = c[n] * mpmath.factorial(n) / mpmath.factorial(n - j) * Y ** (n - j)
+                    lo_j += min(term, 0)
+                    hi_j += max(term, 0)
+                cj = comb(N - 1, j)
+                t_lo += min(lo_j - e_row, 0) * cj
+                t_hi += max(hi_j + e_row, 0) * cj
+            one = mpf(2) ** -64
+            lo = -(mu + t_hi + one)
+            width = 2 * eps + 2 * mu + (t_hi - t_lo) + (N + 1) * one
+            s64 = mpf(2) ** 64
+            win[row, 0] = int(mpmath.floor(lo * s64)) % M64
+            win[row, 1] = min(int(mpmath.ceil(width * s64)) + 2, M64 - 1)
+            thr[row, 0] = int(mpmath.ceil(mu * s64))
+            thr[row, 1] = int(mpmath.floor((2 * eps - mu) * s64)) - 1
+            thr[row, 2] = int(mpmath.ceil((2 * eps + mu) * s64))
+            thr[row, 3] = int(mpmath.floor((1 - mu) * s64)) - 1
+    return Prepared(spec, subs, tables, win, thr, h, uf)
+
+
+def is_hr(spec: JobSpec, m: int, uf=None, prec: int = 192) -> bool:
+    """Exact decision for one argument offset m (high-precision evaluation)."""
+    uf = output_ulp(spec) if uf is None else uf
+    with mpmath.workprec(prec):
+        X = mpf(spec.X0) + m * _ulp(spec.X0)
+        y = _f(spec.fname, X) / uf
+        if spec.mode == "rn":
+            y -= mpf(1) / 2
+        dist = abs(y - mpmath.nint(y))
+        eps = mpf(2) ** (-spec.s)
+        if abs(dist - eps) < mpf(2) ** (64 - prec):
+            if prec >= 4096:
+                raise ArithmeticError("undecidable at 4096 bits")
+            return is_hr(spec, m, uf, 2 * prec)
+        return bool(dist < eps)

@@ -1,0 +1,73 @@
+"""Seeded synthetic workloads (inputs only; none of the method's arithmetic).
+
+Shared by the tests, the bench and the oracle's callers.  Workloads are
+shaped like the paper's (exp over binary64 sub-ranges of [1, 2), directed or
+round-to-nearest HR thresholds), with random instances where the paper's
+inputs are themselves arbitrary fractions.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# Plain degree-1 search: 4096 random (a, b), N = 2^16, threshold 2^-20.
+CONFIG1 = dict(n=4096, N=1 << 16, D=1 << 44, seed=1)
+
+# Plain pipeline, small: exp on [1, 1 + 2^-20) = 2^32 arguments, 256
+# sub-intervals of 2^24, degree 3 at 192 bits, pieces of N = 2^16 (tau = 256),
+# round-to-nearest, eps = 2^-24 ulp.
+CONFIG2 = dict(fname="exp", X0=1.0, count=1 << 32, s=24, mode="rn",
+               N=1 << 16, tau=1 << 8, delta=3, W=192)
+
+# Plain pipeline, large: exp on [1, 1 + 2^-12) = 2^40 arguments, 4096
+# sub-intervals of 2^28, degree 4 at 256 bits, N = 2^18 (tau = 1024),
+# round-to-nearest, eps = 2^-32 ulp.
+CONFIG3 = dict(fname="exp", X0=1.0, count=1 << 40, s=32, mode="rn",
+               N=1 << 18, tau=1 << 10, delta=4, W=256)
+
+
+def rng(seed: int, stream: int = 0) -> np.random.Generator:
+    """numpy PCG64 generator for (seed, stream)."""
+    return np.random.Generator(np.random.PCG64([seed, stream]) if stream else np.random.PCG64(seed))
+
+
+def config1(seed: int = CONFIG1["seed"], n: int = CONFIG1["n"], N: int = CONFIG1["N"],
+            D: int = CONFIG1["D"]):
+    """(A, B, N[], D): A then B drawn uniformly from [0, 2^64)."""
+    g = rng(seed)
+    A = g.integers(0, 2 ** 64, n, dtype=np.uint64, endpoint=False)
+    B = g.integers(0, 2 ** 64, n, dtype=np.uint64, endpoint=False)
+    return A, B, np.full(n, N, np.uint32), D
+
+
+def adversarial_instances(seed: int, n: int, max_N: int = 5000):
+    """Instances hitting the degenerate corners: a = 0, powers of two, long
+    runs of trailing zeros (short periods), a near 0 or 1, tiny and empty N,
+    windows from empty to full."""
+    g = rng(seed)
+    A = g.integers(0, 2 ** 64, n, dtype=np.uint64, endpoint=False)
+    B = g.integers(0, 2 ** 64, n, dtype=np.uint64, endpoint=False)
+    kind = g.integers(0, 8, n)
+    sh = g.integers(0, 64, n).astype(np.uint64)
+    small = g.integers(0, 1000, n).astype(np.uint64)
+    with np.errstate(over="ignore"):
+        A = np.where(kind == 1, A >> sh, A)
+        A = np.where(kind == 2, ~(A >> sh), A)
+        A = np.where(kind == 3, small << sh, A)
+        A = np.where(kind == 4, np.uint64(0), A)
+        A = np.where(kind == 5, np.uint64(1) << sh, A)
+    Nk = g.integers(0, 4, n)
+    N = np.where(Nk == 0, g.integers(0, 4, n),
+                 np.where(Nk == 1, g.integers(0, 300, n), g.integers(0, max_N, n))).astype(np.uint32)
+    Dk = g.integers(0, 5, n)
+    Dr = g.integers(0, 2 ** 64, n, dtype=np.uint64, endpoint=False)
+    D = np.where(Dk == 0, Dr, np.where(Dk == 1, Dr >> sh, np.where(Dk == 2, np.uint64(2 ** 64 - 1),
+                 np.where(Dk == 3, g.integers(0, 3, n).astype(np.uint64), np.uint64(1) << (sh | np.uint64(32))))))
+    lo = np.where(g.integers(0, 2, n) == 0, np.uint64(0), g.integers(0, 2 ** 64, n, dtype=np.uint64, endpoint=False))
+    return A, B, N, lo, D.astype(np.uint64)
+
+
+def random_tables(seed: int, n_sub: int, delta: int, W: int):
+    """Uniformly random initial tables: uint64 (n_sub, E, W/64)."""
+    g = rng(seed)
+    E = (delta + 1) * (delta + 2) // 2
+    return g.integers(0, 2 ** 64, (n_sub, E, W // 64), dtype=np.uint64, endpoint=False)

@@ -1,0 +1,44 @@
+"""CPU checks of the C ABI: the library loads and exports what the header declares."""
+import ctypes
+import re
+
+import pytest
+
+from paper_1211_3056_amd import _lib
+
+
+def _declared():
+    text = open(_lib.HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hr_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert sorted(_lib.EXPORTS) == _declared()
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def test_version_and_status_strings():
+    L = _lib.lib()
+    assert L.hr_abi_version() == 1
+    assert _lib.status_str(0) == "ok"
+    assert "invalid" in _lib.status_str(-1)
+    assert _lib.status_str(12345) == "unknown status"
+
+
+def test_invalid_arguments_rejected_before_any_device_call():
+    L = _lib.lib()
+    P = ctypes.c_void_p
+    assert L.hr_create(None, 0) == _lib.HR_EINVAL
+    assert L.hr_search(None, None, None, None, 0, None, None, 1, None, None, None, None, 0, None, None) == _lib.HR_EINVAL
+    assert L.hr_tabulate(None, None, 1, 3, 16, 192, None, None, None) == _lib.HR_EINVAL
+    assert L.hr_destroy(None) == _lib.HR_OK
+
+
+def test_result_record_layout():
+    assert _lib.RESULT_BYTES == 24

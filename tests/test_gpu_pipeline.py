@@ -1,0 +1,70 @@
+"""GPU HR-case lists against the oracle: small ranges, config 2 in full,
+config 3 on sampled sub-intervals.  Fused and plain forms must agree."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import synth
+from oracle import hr as ohr
+from oracle.taylor import Job
+
+pytestmark = pytest.mark.gpu
+
+STARTS = {"exp": 1.0, "exp2": 1.0, "log": 3.37, "sin": 1.0, "cos": 1.0}
+
+
+@pytest.mark.parametrize("fname", ["exp", "exp2", "log", "sin", "cos"])
+@pytest.mark.parametrize("mode", ["rn", "dir"])
+def test_small_ranges_equal_bruteforce(fname, mode):
+    from paper_1211_3056_amd import pipeline
+    from paper_1211_3056_amd.prep import JobSpec
+    args = (fname, STARTS[fname], 1 << 14, 8, mode, 1 << 6, 1 << 4, 3, 128)
+    ref = ohr.hr_bruteforce(Job(*args))
+    assert len(ref) > 30
+    fused, _ = pipeline.search_job(JobSpec(*args), "fused")
+    plain, _ = pipeline.search_job(JobSpec(*args), "plain")
+    assert fused == ref
+    assert plain == ref
+
+
+@pytest.mark.parametrize("W,delta", [(192, 3), (256, 4), (128, 2)])
+def test_word_widths_and_degrees(W, delta):
+    from paper_1211_3056_amd import pipeline
+    from paper_1211_3056_amd.prep import JobSpec
+    args = ("exp", 1.125, 1 << 15, 9, "rn", 1 << 7, 1 << 5, delta, W)
+    ref = ohr.hr_bruteforce(Job(*args))
+    got, _ = pipeline.search_job(JobSpec(*args), "fused")
+    assert got == ref
+
+
+def test_config2_full_list():
+    """exp on 2^32 arguments of [1, 1 + 2^-20), eps = 2^-24, RN: the GPU list
+    equals the three-phase oracle's list, fused and plain."""
+    from paper_1211_3056_amd import pipeline
+    from paper_1211_3056_amd.prep import JobSpec
+    spec = JobSpec(**synth.CONFIG2)
+    fused, st = pipeline.search_job(spec, "fused")
+    plain, st2 = pipeline.search_job(spec, "plain")
+    ref = ohr.pipeline(Job(**synth.CONFIG2))
+    assert fused == ref
+    assert plain == ref
+    assert 400 < len(ref) < 640            # 2 eps 2^32 = 512 expected
+    assert st["candidates"] == st2["candidates"]
+
+
+def test_config3_sampled_subintervals():
+    """exp on 2^40 arguments, eps = 2^-32: the full device run, compared on
+    sampled whole sub-intervals with the oracle."""
+    from paper_1211_3056_amd import pipeline
+    from paper_1211_3056_amd.prep import JobSpec
+    spec = JobSpec(**synth.CONFIG3)
+    got, st = pipeline.search_job(spec, "fused")
+    assert 400 < len(got) < 640            # 2 eps 2^40 = 512 expected
+    assert st["pieces"] == 1 << 22
+    job = Job(**synth.CONFIG3)
+    with_cases = sorted({m // spec.per_sub for m in got})
+    for t in [0, 1777, 4095] + with_cases[:: max(1, len(with_cases) // 3)][:3]:
+        ref = ohr.pipeline(job, subs=[t])
+        lo, hi = t * spec.per_sub, (t + 1) * spec.per_sub
+        assert [m for m in got if lo <= m < hi] == ref

@@ -1,0 +1,101 @@
+"""GPU parity of hr_tabulate and hr_recheck against the oracle (bit-exact)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import synth
+from oracle import tabulate as otab
+from oracle.taylor import Job, initial_table
+
+pytestmark = pytest.mark.gpu
+
+
+def _words(tables_np, delta):
+    """uint64 (n_sub, E, L) -> per sub-interval T[j][l] as Python ints."""
+    n_sub, E, L = tables_np.shape
+    out = []
+    for s in range(n_sub):
+        flat = [sum(int(tables_np[s, e, l]) << (64 * l) for l in range(L)) for e in range(E)]
+        T, pos = [], 0
+        for j in range(delta + 1):
+            T.append(flat[pos:pos + delta - j + 1])
+            pos += delta - j + 1
+        out.append(T)
+    return out
+
+
+def _pack(T, W):
+    L = W // 64
+    flat = [v for row in T for v in row]
+    return np.array([[(v >> (64 * l)) & ((1 << 64) - 1) for l in range(L)] for v in flat], np.uint64)
+
+
+@pytest.mark.parametrize("W", [128, 192, 256])
+@pytest.mark.parametrize("delta,tau", [(1, 5), (2, 77), (3, 256), (4, 1000), (5, 130), (6, 33)])
+def test_tabulate_random_tables(W, delta, tau):
+    from paper_1211_3056_amd import api
+    n_sub = 3
+    tabs = synth.random_tables(100 * W + delta, n_sub, delta, W)
+    a, b = api.tabulate(api.to_dev(tabs.reshape(-1), torch.uint64), n_sub, delta, tau, W)
+    a, b = a.cpu().numpy(), b.cpu().numpy()
+    ra, rb = otab.tabulate(_words(tabs, delta), delta, tau, W)
+    assert a.tolist() == ra and b.tolist() == rb
+
+
+def test_tabulate_exp_tables_from_oracle():
+    """Tables of exp written by the oracle (degree 4, 256 bits, tau = 1024)."""
+    from paper_1211_3056_amd import api
+    job = Job("exp", 1.0, 1 << 40, 32, "rn", 1 << 18, 1 << 10, 4, 256)
+    subs = [0, 2047, 4095]
+    Ts = [initial_table(job, t) for t in subs]
+    tabs = np.stack([_pack(T, 256) for T in Ts])
+    a, b = api.tabulate(api.to_dev(tabs.reshape(-1), torch.uint64), len(subs), 4, 1 << 10, 256)
+    ra, rb = otab.tabulate(Ts, 4, 1 << 10, 256)
+    assert a.cpu().numpy().tolist() == ra and b.cpu().numpy().tolist() == rb
+
+
+@pytest.mark.parametrize("W,delta", [(128, 3), (192, 3), (256, 4), (256, 6)])
+def test_recheck_random(W, delta):
+    from paper_1211_3056_amd import api
+    n_sub, tau, N = 4, 300, 1 << 14
+    tabs = synth.random_tables(7 * W + delta, n_sub, delta, W)
+    g = synth.rng(W + delta)
+    nc = 3000
+    inst = g.integers(0, n_sub * tau, nc).astype(np.uint32)
+    k = g.integers(0, N, nc).astype(np.uint32)
+    k[:5] = [0, 1, N - 1, 2, 3]
+    thr = np.zeros((n_sub, 4), np.uint64)
+    thr[:, 0], thr[:, 1] = 1 << 40, 1 << 62
+    thr[:, 2], thr[:, 3] = (1 << 62) + (1 << 40), (1 << 64) - (1 << 40)
+    value, cls = api.recheck(api.to_dev(tabs.reshape(-1), torch.uint64), n_sub, delta, tau, W,
+                             api.to_dev(inst, torch.uint32), api.to_dev(k, torch.uint32), N - 1,
+                             api.to_dev(thr.reshape(-1), torch.uint64))
+    value, cls = value.cpu().numpy(), cls.cpu().numpy()
+    Ts = _words(tabs, delta)
+    for c in range(nc):
+        s, i = divmod(int(inst[c]), tau)
+        V = otab.evaluate(otab.straightforward_rows(Ts[s], delta, i, W), int(k[c]), W)
+        t = otab.top64(V, W)
+        assert int(value[c]) == t
+        want = 1 if thr[s, 0] <= t <= thr[s, 1] else (0 if thr[s, 2] <= t <= thr[s, 3] else 2)
+        assert int(cls[c]) == want
+
+
+def test_tabulate_config3_full_size_sampled():
+    """All 2^22 pieces of the 2^40-argument exp workload on the device from
+    the product's tables; sampled pieces against the oracle's own tables."""
+    from paper_1211_3056_amd import api
+    from paper_1211_3056_amd.prep import JobSpec, prepare
+    spec = JobSpec(**synth.CONFIG3)
+    P = prepare(spec)
+    a, b = api.tabulate(api.to_dev(P.tables.reshape(-1), torch.uint64), spec.n_sub, spec.delta,
+                        spec.tau, spec.W)
+    a, b = a.cpu().numpy(), b.cpu().numpy()
+    job = Job(**synth.CONFIG3)
+    g = synth.rng(33)
+    for t in [0, 1, 4095] + g.integers(0, spec.n_sub, 5).tolist():
+        T = initial_table(job, int(t))
+        for i in [0, 1, 511, 1023] + g.integers(0, spec.tau, 4).tolist():
+            ra, rb = otab.piece_ab(otab.straightforward_rows(T, 4, int(i), 256), 256)
+            assert (int(a[t * spec.tau + i]), int(b[t * spec.tau + i])) == (ra, rb)
