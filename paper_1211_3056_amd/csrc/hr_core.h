@@ -73,8 +73,9 @@ struct Near {
 };
 
 HR_HD void closest_left(uint64_t a, uint64_t b, uint64_t n, Near& r) {
-    uint64_t p = a, q;
+    uint64_t p = a, q = 0;
     uint64_t ip = 1, iq = 0, X = 0, d = b;
+    uint64_t u, v, alpha, beta;
     uint32_t steps = 1;
     // First quotient: q is 1 (2^64), which does not fit; floor(2^64 / a) is
     // floor((2^64 - 1) / a) plus one when a divides 2^64.
@@ -87,56 +88,62 @@ HR_HD void closest_left(uint64_t a, uint64_t b, uint64_t n, Near& r) {
         d -= s * a;
     }
     if (1 + k >= n) {
-        r.x = X; r.d = d;
-        r.u = 1; r.alpha = a;
-        const uint64_t sv = umin(k, n - 1);
-        r.v = sv; r.beta = 0 - sv * a;
-        r.steps = steps;
-        return;
-    }
-    q = 0 - k * a;   // 2^64 mod a
-    iq = k;
-    for (;;) {
-        ++steps;
-        if (p < q) {
-            k = quot_sat(q, p, n);
-            if (X >= iq) {   // b inside a q-interval: it is split at p, 2p, ..
-                const uint64_t s = umin(umin(quot_sat(d, p, n), k), (n - 1 - X) / ip);
-                X += s * ip;
-                d -= s * p;
-            }
-            if (ip + iq + k * ip >= n) {
-                r.x = X; r.d = d;
-                r.u = ip; r.alpha = p;
-                const uint64_t sv = umin(k, (n - 1 - iq) / ip);
-                r.v = iq + sv * ip; r.beta = q - sv * p;
-                r.steps = steps;
-                return;
-            }
-            q -= k * p;
-            iq += k * ip;
-        } else {
-            k = quot_sat(p, q, n);
-            if (X < iq) {    // b inside a p-interval: points at p - q, p - 2q, ..
-                // the first of them at or left of b: s = ceil((p - d) / q)
-                const uint64_t s = quot_sat(p - d - 1, q, n) + 1;
-                if (s <= k && X + ip + s * iq < n) {
-                    X += ip + s * iq;
-                    d -= p - s * q;
+        u = 1;
+        alpha = a;
+        v = umin(k, n - 1);
+        beta = 0 - v * a;
+    } else {
+        q = 0 - k * a;   // 2^64 mod a
+        iq = k;
+        for (;;) {
+            ++steps;
+            if (p < q) {
+                k = quot_sat(q, p, n);
+                if (X >= iq) {   // b inside a q-interval: it is split at p, 2p, ..
+                    const uint64_t s = umin(umin(quot_sat(d, p, n), k), (n - 1 - X) / ip);
+                    X += s * ip;
+                    d -= s * p;
                 }
+                if (ip + iq + k * ip >= n) {
+                    const uint64_t sv = umin(k, (n - 1 - iq) / ip);
+                    u = ip;
+                    alpha = p;
+                    v = iq + sv * ip;
+                    beta = q - sv * p;
+                    break;
+                }
+                q -= k * p;
+                iq += k * ip;
+            } else {
+                k = quot_sat(p, q, n);
+                if (X < iq) {    // b inside a p-interval: points at p - q, p - 2q, ..
+                    // the first of them at or left of b: s = ceil((p - d) / q)
+                    const uint64_t s = quot_sat(p - d - 1, q, n) + 1;
+                    if (s <= k && X + ip + s * iq < n) {
+                        X += ip + s * iq;
+                        d -= p - s * q;
+                    }
+                }
+                if (ip + iq + k * iq >= n) {
+                    const uint64_t su = umin(k, (n - 1 - ip) / iq);
+                    v = iq;
+                    beta = q;
+                    u = ip + su * iq;
+                    alpha = p - su * q;
+                    break;
+                }
+                p -= k * q;
+                ip += k * iq;
             }
-            if (ip + iq + k * iq >= n) {
-                r.x = X; r.d = d;
-                r.v = iq; r.beta = q;
-                const uint64_t su = umin(k, (n - 1 - ip) / iq);
-                r.u = ip + su * iq; r.alpha = p - su * q;
-                r.steps = steps;
-                return;
-            }
-            p -= k * q;
-            ip += k * iq;
         }
     }
+    r.x = X;
+    r.d = d;
+    r.u = u;
+    r.v = v;
+    r.alpha = alpha;
+    r.beta = beta;
+    r.steps = steps;
 }
 
 // Next point to the left of point x among the n points (three-distance
@@ -154,43 +161,82 @@ HR_HD void pred(const Near& r, uint64_t n, uint64_t& x, uint64_t& gap) {
     }
 }
 
-// Degree-1 search of one instance: every k < n with (b - k a) mod 2^64 < D,
-// visited by increasing distance (ties, which only occur between repeated
-// points, by increasing k); emit(k) is called once per hit.  Returns the
-// number of hits.
+// Resumable enumeration of the hits of one instance: every k < n with
+// (b - k a) mod 2^64 < D, produced by increasing distance (ties, which only
+// occur between repeated points, by increasing k).
 //
-// Degenerate inputs: a = 0 puts every point at 0; when the sequence has a
-// period P = 2^(64 - ctz(a)) < n the distinct points are k < P and each
-// reappears at k + m P.
+// Degenerate inputs: a = 0 puts every point at 0 and n = 1 has one point
+// (P = 1 distinct point); when the sequence has a period
+// P = 2^(64 - ctz(a)) < n the distinct points are k < P and each reappears
+// at k + m P.
+struct HitIter {
+    Near r;
+    uint64_t n, P, D;
+    uint64_t x;        // current distinct point
+    uint64_t dist;     // its distance
+    uint64_t k;        // next repeat of x to report
+    uint64_t visited;  // distinct points reported so far
+    bool done;
+};
+
+HR_HD void iter_init(HitIter& it, uint64_t a, uint64_t b, uint64_t n, uint64_t D,
+                     uint32_t* steps = nullptr) {
+    it.n = n;
+    it.D = D;
+    it.done = (n == 0 || D == 0);
+    if (steps) *steps = 0;
+    if (it.done) return;
+    if (a == 0 || n == 1) {
+        it.P = 1;
+        it.x = 0;
+        it.dist = b;
+    } else {
+        it.P = n;
+        const int tz = __builtin_ctzll(a);
+        if (tz > 32 && (1ull << (64 - tz)) < n) it.P = 1ull << (64 - tz);
+        closest_left(a, b, it.P, it.r);
+        if (steps) *steps = it.r.steps;
+        it.x = it.r.x;
+        it.dist = it.r.d;
+    }
+    it.done = it.dist >= D;
+    it.k = it.x;
+    it.visited = 1;
+}
+
+// Next hit into k; false when there is none left.
+HR_HD bool iter_next(HitIter& it, uint64_t& k) {
+    if (it.done) return false;
+    k = it.k;
+    it.k += it.P;
+    if (it.k >= it.n) {          // all repeats of x reported: go left
+        if (it.visited == it.P) {
+            it.done = true;
+        } else {
+            uint64_t gap;
+            pred(it.r, it.P, it.x, gap);
+            if (gap >= it.D - it.dist) {
+                it.done = true;
+            } else {
+                it.dist += gap;
+                it.k = it.x;
+                ++it.visited;
+            }
+        }
+    }
+    return true;
+}
+
+// Calls emit(k) for every hit, in the order above; returns their number.
 template <class Emit>
 HR_HD uint64_t search_each(uint64_t a, uint64_t b, uint64_t n, uint64_t D, Emit&& emit,
                            uint32_t* steps = nullptr) {
-    if (n == 0 || D == 0) return 0;
-    if (a == 0 || n == 1) {
-        if (b >= D) return 0;
-        const uint64_t c = (a == 0) ? n : 1;
-        for (uint64_t k = 0; k < c; ++k) emit(k);
-        return c;
-    }
-    uint64_t P = n;
-    const int tz = __builtin_ctzll(a);
-    if (tz > 32 && (1ull << (64 - tz)) < n) P = 1ull << (64 - tz);
-    Near r;
-    closest_left(a, b, P, r);
-    if (steps) *steps = r.steps;
-    if (r.d >= D) return 0;
-    uint64_t x = r.x, dist = r.d, count = 0, visited = 0;
-    for (;;) {
-        // point x and its repeats x + m P < n share the distance
-        for (uint64_t k = x; k < n; k += P) {
-            emit(k);
-            ++count;
-        }
-        if (++visited == P) break;
-        uint64_t gap;
-        pred(r, P, x, gap);
-        if (gap >= D - dist) break;
-        dist += gap;
+    HitIter it;
+    iter_init(it, a, b, n, D, steps);
+    uint64_t k, count = 0;
+    while (iter_next(it, k)) {
+        emit(k);
+        ++count;
     }
     return count;
 }
@@ -247,26 +293,34 @@ HR_HD void wmac128(Word<L>& acc, const Word<L>& x, const uint32_t m[4]) {
     }
 }
 
-// Inverse of an odd number modulo 2^128 (Newton iteration; o * o = 1 mod 8).
-HR_HD unsigned __int128 inv_odd128(unsigned __int128 o) {
-    unsigned __int128 v = o;
-    for (int i = 0; i < 6; ++i) v *= (unsigned __int128)2 - o * v;
-    return v;
+// Binomials C(x, 1..J) as exact 128-bit integers, incrementally:
+// C(x, j) = C(x, j-1) (x - j + 1) / j, the division being exact (by 2 and 4
+// a shift, by 3, 5 and 6 a multiplication by the inverse of the odd part
+// modulo 2^128).  Valid while x^J < 2^128.
+HR_HD void binoms128(uint64_t x, int J, unsigned __int128* c) {
+    // inverses of 3, 5, 15 and 45 modulo 2^128
+    const unsigned __int128 inv3 = ((unsigned __int128)0xaaaaaaaaaaaaaaaaull << 64) | 0xaaaaaaaaaaaaaaabull;
+    const unsigned __int128 inv5 = ((unsigned __int128)0xccccccccccccccccull << 64) | 0xcccccccccccccccdull;
+    unsigned __int128 v = x;
+    c[0] = v;                                        // C(x, 1)
+    for (int j = 2; j <= J; ++j) {
+        if (x + 1 < (uint64_t)j) { c[j - 1] = 0; continue; }
+        v = v * (unsigned __int128)(x - (uint64_t)(j - 1));
+        // v = x (x-1) .. (x-j+1) / (j-1)!  ->  divide by j
+        if (j == 2) v >>= 1;
+        else if (j == 3) v *= inv3;
+        else if (j == 4) v >>= 2;
+        else if (j == 5) v *= inv5;
+        else if (j == 6) { v >>= 1; v *= inv3; }
+        c[j - 1] = v;
+    }
 }
 
-// Binomial C(x, j) as an exact 128-bit integer: the falling factorial
-// x (x-1) .. (x-j+1) divided exactly by j! (shift out its power of two,
-// multiply by the inverse of its odd part).  Valid while x^j < 2^128.
 HR_HD unsigned __int128 binom128(uint64_t x, int j) {
-    if (x < (uint64_t)j) return 0;
-    unsigned __int128 c = 1;
-    uint64_t f = 1;
-    for (int i = 0; i < j; ++i) {
-        c *= (unsigned __int128)(x - (uint64_t)i);
-        f *= (uint64_t)(i + 1);
-    }
-    const int s = __builtin_ctzll(f);
-    return (c >> s) * inv_odd128((unsigned __int128)(f >> s));
+    if (j == 0) return 1;
+    unsigned __int128 c[6];
+    binoms128(x, j, c);
+    return c[j - 1];
 }
 
 HR_HD void split128(unsigned __int128 v, uint32_t m[4]) {

@@ -16,6 +16,8 @@
 #include <stdint.h>
 #include <stdlib.h>
 
+#include <type_traits>
+
 #include "../../include/hrsearch.h"
 #include "hr_core.h"
 
@@ -152,46 +154,52 @@ __device__ __forceinline__ uint64_t neg_top64(const hr::Word<L>& w) {
     return 0 - (top64(w) + (low != 0));
 }
 
-// acc += T * C(x, m)  (m = 0: plain add)
-template <int L>
-__device__ __forceinline__ void mac_binom(hr::Word<L>& acc, const hr::Word<L>& T, uint64_t x, int m) {
-    if (m == 0) {
-        hr::wadd(acc, T);
-    } else {
-        uint32_t c[4];
-        hr::split128(hr::binom128(x, m), c);
-        hr::wmac128(acc, T, c);
-    }
-}
-
 __host__ __device__ constexpr int n_entries(int deg) { return (deg + 1) * (deg + 2) / 2; }
 __host__ __device__ constexpr int entry(int deg, int j, int l) {
     return j * (deg + 1) - j * (j - 1) / 2 + l;
 }
 
-// Difference vector of row j at piece i0: v[l] = Delta^l r_j(i0) =
-// sum_m T[j][l+m] C(i0, m)  (straightforward shift, Sec. 5.2).
-template <int L, int DEG>
-__device__ __forceinline__ void row_start(const uint64_t* __restrict__ T, int j, uint64_t i0,
+// Multiplier limbs of C(x, 1..DEG) (c[m-1] = C(x, m)).
+template <int DEG>
+__device__ __forceinline__ void binom_limbs(uint64_t x, uint32_t (*c)[4]) {
+    unsigned __int128 b[DEG];
+    hr::binoms128(x, DEG, b);
+#pragma unroll
+    for (int m = 0; m < DEG; ++m) hr::split128(b[m], c[m]);
+}
+
+// Compile-time loop: f(std::integral_constant<int, I>) for I in [B, E).
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+// Difference vector of row J at piece i0: v[l] = Delta^l r_J(i0) =
+// sum_m T[J][l+m] C(i0, m)  (straightforward shift, Sec. 5.2).
+template <int L, int DEG, int J>
+__device__ __forceinline__ void row_start(const uint64_t* __restrict__ T, const uint32_t (*c)[4],
                                           hr::Word<L>* v) {
 #pragma unroll
-    for (int l = 0; l <= DEG - j; ++l) {
-        hr::wzero(v[l]);
+    for (int l = 0; l <= DEG - J; ++l) {
+        load_word<L>(T + (size_t)entry(DEG, J, l) * (L / 2), v[l]);
 #pragma unroll
-        for (int m = 0; l + m <= DEG - j; ++m) {
+        for (int m = 1; l + m <= DEG - J; ++m) {
             hr::Word<L> t;
-            load_word<L>(T + (size_t)entry(DEG, j, l + m) * (L / 2), t);
-            mac_binom(v[l], t, i0, m);
+            load_word<L>(T + (size_t)entry(DEG, J, l + m) * (L / 2), t);
+            hr::wmac128(v[l], t, c[m - 1]);
         }
     }
 }
 
-// One tabulated-difference step of a difference vector of length len
+// One tabulated-difference step of a difference vector of length LEN
 // (Fig. 7: Delta^l(i+1) = Delta^l(i) + Delta^{l+1}(i)).
-template <int L>
-__device__ __forceinline__ void row_step(hr::Word<L>* v, int len) {
+template <int L, int LEN>
+__device__ __forceinline__ void row_step(hr::Word<L>* v) {
 #pragma unroll
-    for (int l = 0; l + 1 < len; ++l) hr::wadd(v[l], v[l + 1]);
+    for (int l = 0; l + 1 < LEN; ++l) hr::wadd(v[l], v[l + 1]);
 }
 
 // ---------------------------------------------------------------- tabulate
@@ -209,14 +217,16 @@ __global__ __launch_bounds__(kBlock) void k_tabulate(const uint64_t* __restrict_
     const uint32_t cnt = (uint32_t)hr::umin(nu, tau - i0);
     const uint64_t* T = table + sub * n_entries(DEG) * (L / 2);
     hr::Word<L> v0[DEG + 1], v1[DEG];
-    row_start<L, DEG>(T, 0, i0, v0);
-    row_start<L, DEG>(T, 1, i0, v1);
+    uint32_t cb[DEG][4];
+    binom_limbs<DEG>(i0, cb);
+    row_start<L, DEG, 0>(T, cb, v0);
+    row_start<L, DEG, 1>(T, cb, v1);
     const uint64_t base = sub * tau + i0;
     for (uint32_t s = 0; s < cnt; ++s) {
         b_out[base + s] = top64(v0[0]);
         a_out[base + s] = neg_top64(v1[0]);
-        row_step(v0, DEG + 1);
-        row_step(v1, DEG);
+        row_step<L, DEG + 1>(v0);
+        row_step<L, DEG>(v1);
     }
 }
 
@@ -248,19 +258,23 @@ __global__ __launch_bounds__(kBlock) void k_recheck(const uint64_t* __restrict__
     }
     const uint64_t sub = inst / tau, i = inst % tau;
     const uint64_t* T = table + sub * n_entries(DEG) * (L / 2);
+    uint32_t ci[DEG][4], ck_[DEG][4];
+    binom_limbs<DEG>(i, ci);
+    binom_limbs<DEG>(k, ck_);
     hr::Word<L> V;
     hr::wzero(V);
 #pragma unroll
     for (int j = 0; j <= DEG; ++j) {
         hr::Word<L> r;
-        hr::wzero(r);
+        load_word<L>(T + (size_t)entry(DEG, j, 0) * (L / 2), r);
 #pragma unroll
-        for (int l = 0; l <= DEG - j; ++l) {
+        for (int l = 1; l <= DEG - j; ++l) {
             hr::Word<L> t;
             load_word<L>(T + (size_t)entry(DEG, j, l) * (L / 2), t);
-            mac_binom(r, t, i, l);
+            hr::wmac128(r, t, ci[l - 1]);
         }
-        mac_binom(V, r, k, j);
+        if (j == 0) hr::wadd(V, r);
+        else hr::wmac128(V, r, ck_[j - 1]);
     }
     const uint64_t t = top64(V);
     value_out[c] = t;
@@ -269,43 +283,113 @@ __global__ __launch_bounds__(kBlock) void k_recheck(const uint64_t* __restrict__
 
 // ---------------------------------------------------------------- pipeline
 
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Fused pass over whole sub-intervals, one wave per workgroup.  Each lane
+// owns a packet of nu consecutive pieces of one sub-interval and keeps the
+// full difference table of all rows r_0..r_DEG in registers (packet start by
+// straightforward shift, then one tabulated-difference step per piece).
+// For its current piece a lane runs the exact degree-1 search; candidates
+// are compacted into an LDS queue (ballot + mbcnt) together with the
+// piece rows, and all 64 lanes then recheck queued candidates in parallel,
+// so that the uneven number of candidates per piece does not idle lanes.
+constexpr int kQueue = 512;
+
 template <int L, int DEG>
-__global__ __launch_bounds__(kBlock) void k_pipeline(
+__global__ __launch_bounds__(64) void k_pipeline(
     const uint64_t* __restrict__ table, uint32_t n_sub, uint32_t tau, uint32_t nu, uint32_t N,
     const uint64_t* __restrict__ win, const uint64_t* __restrict__ thr, hr_result* __restrict__ out,
     uint64_t cap, unsigned long long* __restrict__ count, unsigned long long* __restrict__ stats) {
-    const uint64_t gid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    constexpr int E = n_entries(DEG);
+    __shared__ uint32_t s_rows[(DEG + 1) * L * 64];   // word-major: [(j L + w) * 64 + lane]
+    __shared__ uint32_t s_qlane[kQueue];
+    __shared__ uint32_t s_qk[kQueue];
+    const int lane = threadIdx.x;
     const uint64_t per_sub = (tau + nu - 1) / nu;
-    uint64_t n_pieces = 0, n_cand = 0, n_res = 0, n_steps = 0;
-    if (gid < (uint64_t)n_sub * per_sub) {
-        const uint64_t sub = gid / per_sub;
-        const uint64_t i0 = (gid % per_sub) * nu;
-        const uint32_t cnt = (uint32_t)hr::umin(nu, tau - i0);
-        const uint64_t* T = table + sub * n_entries(DEG) * (L / 2);
-        const uint64_t wlo = win[2 * sub], wd = win[2 * sub + 1];
-        const uint64_t* th = thr + 4 * sub;
-        // full difference table of every row at i0
-        hr::Word<L> v[n_entries(DEG)];
+    const uint64_t gid = (uint64_t)blockIdx.x * 64 + lane;
+    const bool active = gid < (uint64_t)n_sub * per_sub;
+    uint64_t sub = 0, i0 = 0;
+    uint32_t cnt = 0;
+    if (active) {
+        sub = gid / per_sub;
+        i0 = (gid % per_sub) * nu;
+        cnt = (uint32_t)hr::umin(nu, tau - i0);
+    }
+    hr::Word<L> v[E];
+    if (active) {
+        const uint64_t* T = table + sub * E * (L / 2);
+        uint32_t cb[DEG][4];
+        binom_limbs<DEG>(i0, cb);
+        static_for<0, DEG + 1>([&](auto J) {
+            row_start<L, DEG, decltype(J)::value>(T, cb, v + entry(DEG, decltype(J)::value, 0));
+        });
+    } else {
 #pragma unroll
-        for (int j = 0; j <= DEG; ++j) row_start<L, DEG>(T, j, i0, v + entry(DEG, j, 0));
-        for (uint32_t s = 0; s < cnt; ++s) {
-            const uint64_t piece = i0 + s;
+        for (int e = 0; e < E; ++e) hr::wzero(v[e]);
+    }
+    const uint64_t wlo = active ? win[2 * sub] : 0;
+    const uint64_t wd = active ? win[2 * sub + 1] : 0;
+    uint64_t n_pieces = 0, n_cand = 0, n_res = 0, n_steps = 0;
+
+    for (uint32_t s = 0; s < nu; ++s) {
+        const bool live = active && s < cnt;
+#pragma unroll
+        for (int j = 0; j <= DEG; ++j)
+#pragma unroll
+            for (int w = 0; w < L; ++w) s_rows[(j * L + w) * 64 + lane] = v[entry(DEG, j, 0)].w[w];
+        hr::HitIter it;
+        it.done = true;
+        if (live) {
+            uint32_t steps = 0;
             const uint64_t bb = top64(v[entry(DEG, 0, 0)]) - wlo;
             const uint64_t aa = neg_top64(v[entry(DEG, 1, 0)]);
+            hr::iter_init(it, aa, bb, N, wd, &steps);
             ++n_pieces;
-            uint32_t steps = 0;
-            n_cand += hr::search_each(aa, bb, N, wd, [&](uint64_t k) {
-                hr::Word<L> V = v[entry(DEG, 0, 0)];
+            n_steps += steps;
+        }
+        for (;;) {
+            uint32_t qn = 0;
+            for (;;) {   // fill: one hit per lane and round while room remains
+                uint64_t k = 0;
+                const bool has = hr::iter_next(it, k);
+                const uint64_t mask = __ballot(has);
+                if (has) {
+                    const uint32_t pos = qn + lanes_below(mask);
+                    s_qlane[pos] = (uint32_t)lane;
+                    s_qk[pos] = (uint32_t)k;
+                }
+                qn += (uint32_t)__popcll(mask);
+                if (mask == 0 || qn + 64 > kQueue) break;
+            }
+            __syncthreads();
+            for (uint32_t e = lane; e < qn; e += 64) {   // drain
+                const uint32_t src = s_qlane[e];
+                const uint64_t k = s_qk[e];
+                hr::Word<L> V;
 #pragma unroll
-                for (int j = 1; j <= DEG; ++j) mac_binom(V, v[entry(DEG, j, 0)], k, j);
+                for (int w = 0; w < L; ++w) V.w[w] = s_rows[w * 64 + src];
+                uint32_t cb[DEG][4];
+                binom_limbs<DEG>(k, cb);
+#pragma unroll
+                for (int j = 1; j <= DEG; ++j) {
+                    hr::Word<L> r;
+#pragma unroll
+                    for (int w = 0; w < L; ++w) r.w[w] = s_rows[(j * L + w) * 64 + src];
+                    hr::wmac128(V, r, cb[j - 1]);
+                }
                 const uint64_t t = top64(V);
-                const uint8_t cls = classify<L>(t, th);
+                const uint64_t g = (uint64_t)blockIdx.x * 64 + src;
+                const uint64_t ssub = g / per_sub;
+                const uint8_t cls = classify<L>(t, thr + 4 * ssub);
                 if (cls) {
                     const unsigned long long pos = atomicAdd(count, 1ull);
                     if (pos < cap) {
                         hr_result r;
-                        r.sub = (uint32_t)sub;
-                        r.piece = (uint32_t)piece;
+                        r.sub = (uint32_t)ssub;
+                        r.piece = (uint32_t)((g % per_sub) * nu + s);
                         r.k = (uint32_t)k;
                         r.cls = cls;
                         r.value = t;
@@ -313,18 +397,22 @@ __global__ __launch_bounds__(kBlock) void k_pipeline(
                     }
                     ++n_res;
                 }
-            }, &steps);
-            n_steps += steps;
-#pragma unroll
-            for (int j = 0; j <= DEG; ++j) row_step(v + entry(DEG, j, 0), DEG - j + 1);
+                ++n_cand;
+            }
+            __syncthreads();
+            if (__ballot(!it.done) == 0) break;
         }
+        static_for<0, DEG + 1>([&](auto J) {
+            constexpr int j = decltype(J)::value;
+            row_step<L, DEG - j + 1>(v + entry(DEG, j, 0));
+        });
     }
     if (stats) {
         n_pieces = wave_sum(n_pieces);
         n_cand = wave_sum(n_cand);
         n_res = wave_sum(n_res);
         n_steps = wave_sum(n_steps);
-        if ((threadIdx.x & 63) == 0) {
+        if (lane == 0) {
             atomicAdd(stats + 0, (unsigned long long)n_pieces);
             atomicAdd(stats + 1, (unsigned long long)n_cand);
             atomicAdd(stats + 2, (unsigned long long)n_res);
@@ -527,10 +615,10 @@ hr_status hr_pipeline(hr_ctx* ctx, const uint64_t* table, uint32_t n_sub, uint32
     hipStream_t st = as_stream(stream);
     const uint32_t nu = pick_nu(n_sub, tau);
     const uint64_t lanes = (uint64_t)n_sub * ((tau + nu - 1) / nu);
-    const uint64_t blocks = (lanes + kBlock - 1) / kBlock;
+    const uint64_t blocks = (lanes + 63) / 64;
     if (blocks > 0xffffffffull) return HR_EINVAL;
     HR_DISPATCH(width_bits, degree,
-                (k_pipeline<L_, D_><<<dim3((uint32_t)blocks), dim3(kBlock), 0, st>>>(
+                (k_pipeline<L_, D_><<<dim3((uint32_t)blocks), dim3(64), 0, st>>>(
                     table, n_sub, tau, nu, N, win, thr, out, cap,
                     (unsigned long long*)count, (unsigned long long*)stats)));
     return launched();
