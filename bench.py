@@ -35,6 +35,7 @@ def parse():
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--cpu-subs", type=int, default=16,
                    help="sub-intervals in the oracle's timed sample")
+    p.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain workload")
     return p.parse_args()
 
 
@@ -153,6 +154,8 @@ def main():
         line["plain_form"] = {"ms_per_step": min(tp) * 1000,
                               "value": args_total / min(tp), "candidates": pst["candidates"],
                               "hr_cases": len(hr_plain)}
+    if not args.no_batch:
+        line["batch"] = bench_batch(args)
     if not args.no_cpu_baseline:
         from oracle import hr as ohr
         from oracle import native
@@ -167,6 +170,52 @@ def main():
                                 "sample": f"{len(subs)} of {n_sub} sub-intervals "
                                           f"({len(subs) * spec.per_sub} args), {cpu_s:.1f} s"}
     print(json.dumps(line))
+
+
+def bench_batch(args):
+    """16 jobs (exp, log, 2^x, sin; 2^30..2^38 arguments each; N uniform in
+    [2^12, 2^20] per sub-interval; eps = 2^-28): one persistent launch vs one
+    launch per job, same work items, same results."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1211_3056_amd import batch
+
+    jobs = [batch.BatchJob(**d) for d in synth.config4()]
+    plan = batch.build_plan(jobs)
+    dp = batch.DevicePlan(plan)
+    run = batch.Runner(dp)
+    for _ in range(max(1, args.warmup)):
+        run.batched()
+    torch.cuda.synchronize()
+    tb = []
+    for _ in range(max(3, args.steps // 2)):
+        t0 = time.perf_counter()
+        res_b = run.batched()
+        tb.append(time.perf_counter() - t0)
+    st = run.stats_dict()
+    run.plain()
+    tp = []
+    for _ in range(2):
+        t0 = time.perf_counter()
+        res_p = run.plain()
+        tp.append(time.perf_counter() - t0)
+    same = np.array_equal(np.sort(res_b, order=["job", "sub", "piece", "k"]),
+                          np.sort(res_p, order=["job", "sub", "piece", "k"]))
+    hr = batch.finish(plan, res_b)
+    n_args = batch.args_of(plan)
+    b_s, p_s = min(tb), min(tp)
+    return {"workload": "16 jobs exp/log/2^x/sin, 2^30..2^38 args each, N~U[2^12,2^20] "
+                        "per 2^28-arg sub-interval, eps 2^-28 RN",
+            "args": n_args, "sub_intervals": sum(len(pj.subs) for pj in plan.jobs),
+            "items": int(len(plan.items)), "widths": sorted({pj.W for pj in plan.jobs}),
+            "degrees": sorted({pj.delta for pj in plan.jobs}),
+            "batched_ms": b_s * 1000, "plain_ms": p_s * 1000,
+            "batched_args_per_s": n_args / b_s, "plain_args_per_s": n_args / p_s,
+            "speedup": p_s / b_s, "identical_results": bool(same),
+            "hr_cases": sum(len(v) for v in hr.values()), "candidates": st["candidates"],
+            "host_prep_s": plan.prep_s}
 
 
 if __name__ == "__main__":

@@ -141,16 +141,37 @@ hr_status hr_recheck(hr_ctx* ctx, const uint64_t* table, uint32_t n_sub, uint32_
                      const uint64_t* thr, uint64_t* value_out, uint8_t* class_out,
                      void* stream);
 
-/* One result of hr_pipeline: an argument whose piece value passed the
- * exact test (cls 1) or fell inside the error margin (cls 2, to be decided
- * by the caller at higher precision). */
+/* One result of hr_pipeline / hr_batch_run: an argument whose piece value
+ * passed the exact test (cls 1) or fell inside the error margin (cls 2, to
+ * be decided by the caller at higher precision). */
 typedef struct {
+    uint32_t job;      /* job id of the work item (0 for hr_pipeline)    */
     uint32_t sub;      /* sub-interval                                  */
     uint32_t piece;    /* piece inside the sub-interval                  */
     uint32_t k;        /* argument offset inside the piece               */
     uint32_t cls;      /* 1 = HR case, 2 = undecided                     */
+    uint32_t reserved; /* 0                                              */
     uint64_t value;    /* top 64 bits of P_piece(k) mod 1                */
 } hr_result;
+
+/* A batch work item: a range of pieces of one sub-interval.  The pieces of
+ * the sub-interval have N arguments each, except piece `last_piece`, which
+ * has `last_N` (a partial last piece; last_piece = 0xffffffff if none). */
+typedef struct {
+    uint64_t table;     /* offset, in uint64 limbs, of the sub-interval's
+                           table in the table pool (layout of hr_tabulate) */
+    uint64_t win_lo;    /* degree-1 window start (as hr_search's lo)     */
+    uint64_t win_d;     /* degree-1 window width                         */
+    uint64_t thr[4];    /* hr_lo, hr_hi, rej_lo, rej_hi (as hr_recheck)  */
+    uint32_t job;       /* copied into results                           */
+    uint32_t sub;       /* copied into results                           */
+    uint32_t piece0;    /* first piece of the item                       */
+    uint32_t npieces;   /* number of pieces (>= 1)                       */
+    uint32_t nu;        /* pieces per lane: npieces <= 64 * nu            */
+    uint32_t N;         /* arguments per piece                           */
+    uint32_t last_piece;
+    uint32_t last_N;
+} hr_item;
 
 /*
  * hr_pipeline -- fused tabulate + search + recheck of whole sub-intervals in
@@ -170,6 +191,28 @@ hr_status hr_pipeline(hr_ctx* ctx, const uint64_t* table, uint32_t n_sub, uint32
                       uint32_t tau, uint32_t width_bits, uint32_t N, const uint64_t* win,
                       const uint64_t* thr, hr_result* out, uint64_t cap, uint64_t* count,
                       uint64_t* stats, void* stream);
+
+/*
+ * hr_batch_run -- the fused pass over a list of work items of uneven size
+ * (many jobs, functions, binades and piece lengths in one launch).
+ *
+ *  pool        uint64 table pool; item i's table starts at pool + items[i].table
+ *  items       hr_item[n_items] (device)
+ *  width_bits, degree: shared by every item of the call (tables of lower
+ *              degree or width are padded: zero high-order entries, zero low
+ *              limbs, which leaves every result unchanged)
+ *  waves       0: one wave per item (grid = n_items);
+ *              > 0: persistent: `waves` one-wave workgroups claim items from
+ *              a device counter until none is left (every wave exits when the
+ *              list is exhausted)
+ *  out, cap, count, stats: as hr_pipeline (results carry the item's job/sub)
+ * Piece arguments k must satisfy k^degree < 2^128 and piece indices
+ * piece^degree < 2^128 (checked on the host by the caller's planner).
+ * Errors: HR_EINVAL for bad width/degree, null pointers, n_items > 2^31.
+ */
+hr_status hr_batch_run(hr_ctx* ctx, const uint64_t* pool, const hr_item* items, uint32_t n_items,
+                       uint32_t width_bits, uint32_t degree, uint32_t waves, hr_result* out,
+                       uint64_t cap, uint64_t* count, uint64_t* stats, void* stream);
 
 #ifdef __cplusplus
 }

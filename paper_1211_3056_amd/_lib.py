@@ -28,12 +28,21 @@ class HRError(RuntimeError):
 
 
 class hr_result(ctypes.Structure):
-    _fields_ = [("sub", ctypes.c_uint32), ("piece", ctypes.c_uint32), ("k", ctypes.c_uint32),
-                ("cls", ctypes.c_uint32), ("value", ctypes.c_uint64)]
+    _fields_ = [("job", ctypes.c_uint32), ("sub", ctypes.c_uint32), ("piece", ctypes.c_uint32),
+                ("k", ctypes.c_uint32), ("cls", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("value", ctypes.c_uint64)]
+
+
+class hr_item(ctypes.Structure):
+    _fields_ = [("table", ctypes.c_uint64), ("win_lo", ctypes.c_uint64), ("win_d", ctypes.c_uint64),
+                ("thr", ctypes.c_uint64 * 4), ("job", ctypes.c_uint32), ("sub", ctypes.c_uint32),
+                ("piece0", ctypes.c_uint32), ("npieces", ctypes.c_uint32), ("nu", ctypes.c_uint32),
+                ("N", ctypes.c_uint32), ("last_piece", ctypes.c_uint32), ("last_N", ctypes.c_uint32)]
 
 
 RESULT_BYTES = ctypes.sizeof(hr_result)
-EXPORTS = ("hr_abi_version", "hr_status_str", "hr_create", "hr_destroy", "hr_search",
+ITEM_BYTES = ctypes.sizeof(hr_item)
+EXPORTS = ("hr_abi_version", "hr_status_str", "hr_create", "hr_destroy", "hr_search", "hr_batch_run",
            "hr_tabulate", "hr_recheck", "hr_pipeline")
 
 
@@ -62,6 +71,8 @@ def lib():
     L.hr_recheck.argtypes = [P, P, u32, u32, u32, u32, P, P, u64, u32, P, P, P, P]
     L.hr_pipeline.restype = i32
     L.hr_pipeline.argtypes = [P, P, u32, u32, u32, u32, u32, P, P, P, u64, P, P, P]
+    L.hr_batch_run.restype = i32
+    L.hr_batch_run.argtypes = [P, P, P, u32, u32, u32, u32, P, u64, P, P, P]
     _lib = L
     return L
 
@@ -136,3 +147,10 @@ def hr_pipeline(ctx, table, n_sub, degree, tau, width, N, win, thr, out, cap, co
     _check("hr_pipeline", lib().hr_pipeline(ctx.handle, _p(table), n_sub, degree, tau, width, N,
                                             _p(win), _p(thr), _p(out), cap, _p(count), _p(stats),
                                             _stream(stream)))
+
+
+def hr_batch_run(ctx, pool, items, n_items, width, degree, waves, out, cap, count, stats,
+                 stream=None):
+    _check("hr_batch_run", lib().hr_batch_run(ctx.handle, _p(pool), _p(items), n_items, width,
+                                              degree, waves, _p(out), cap, _p(count), _p(stats),
+                                              _stream(stream)))

@@ -1,0 +1,117 @@
+"""Choice of the free parameters of an HR search job.
+
+Rigorous choices (results never depend on them, only speed does):
+
+* degree delta: smallest degree <= 4 whose Lagrange remainder over a whole
+  sub-interval stays below eps 2^-12 (so that undecided values are rare);
+* word width W: smallest of 128, 192, 256 bits whose table-rounding bound
+  2^-W sum_j C(N-1, j) sum_l C(tau-1, l) stays below eps 2^-12 on every
+  sub-interval;
+* piece length N (when the job leaves it free): the power of two that
+  minimises the modelled device time per argument, search cost
+  (~ partial quotients, ~ log N, per piece of N arguments) against recheck
+  cost (candidates ~ window width ~ 2 eps + truncation ~ N^2);
+* work-item split ("waves per sub-interval") and tabulation depth nu (pieces
+  per lane): items of similar modelled cost, 64 lanes x nu pieces each.
+
+The model constants are calibrated from measured runs (``calibrate``) and
+can be overridden; the defaults come from the MI355X measurements of the
+fused pass.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+from math import comb
+
+import mpmath
+from mpmath import mpf
+
+from .prep import _deriv_bound, _taylor_coeffs, _ulp, output_ulp_range
+
+WIDTHS = (128, 192, 256)
+MARGIN_BITS = 12
+
+
+@dataclass
+class CostModel:
+    ns_per_quotient: float = 0.0095     # device ns per partial quotient (whole GPU)
+    ns_per_candidate: float = 0.035     # device ns per rechecked candidate
+    ns_per_piece: float = 0.02          # tabulation, queue and bookkeeping per piece
+
+    def piece_steps(self, N: int) -> float:
+        # partial quotients to reach N points: ~ ln N / (pi^2 / (12 ln 2)) + 1
+        return math.log(max(N, 2)) / 1.1866 + 1.0
+
+    def cost(self, pieces: float, N: int, candidates: float) -> float:
+        return pieces * (self.piece_steps(N) * self.ns_per_quotient + self.ns_per_piece) \
+            + candidates * self.ns_per_candidate
+
+
+MODEL = CostModel()
+
+
+def choose_degree(fname: str, X0: float, sub_len: int, s: int, uf, max_delta: int = 4) -> int:
+    with mpmath.workprec(128):
+        h = _ulp(X0)
+        lim = mpf(2) ** (-s - MARGIN_BITS)
+        for d in range(1, max_delta + 1):
+            n = d + 1
+            ea = _deriv_bound(fname, mpf(X0), mpf(X0) + sub_len * h, n) * (sub_len * h) ** n \
+                / (mpmath.factorial(n) * uf)
+            if ea <= lim:
+                return d
+    raise ValueError("no degree <= %d is accurate enough; use shorter sub-intervals" % max_delta)
+
+
+def choose_width(shapes, delta: int, s: int) -> int:
+    """shapes: iterable of (N, tau) of the job's sub-intervals."""
+    worst = 0
+    for N, tau in set(shapes):
+        sj = sum(comb(N - 1, j) for j in range(delta + 1))
+        sl = sum(comb(tau - 1, l) for l in range(delta + 1))
+        worst = max(worst, sj * sl)
+    need = s + MARGIN_BITS + worst.bit_length()
+    for W in WIDTHS:
+        if W >= need:
+            return W
+    raise ValueError("no supported width is wide enough")
+
+
+def truncation_slope(fname: str, X0: float, uf) -> float:
+    """|r_2| ~ |f''| h^2 / u_f: the truncation error is about this times C(N, 2)."""
+    with mpmath.workprec(80):
+        h = _ulp(X0)
+        c = _taylor_coeffs(fname, mpf(X0), 2, h, uf)
+        return float(abs(2 * c[2]))
+
+
+def choose_N(fname: str, X0: float, count: int, s: int, uf, model: CostModel = MODEL,
+             lo: int = 10, hi: int = 22) -> int:
+    """Power-of-two piece length with the smallest modelled time per argument."""
+    r2 = truncation_slope(fname, X0, uf)
+    eps = 2.0 ** -s
+    best = None
+    for e in range(lo, hi + 1):
+        N = 1 << e
+        width = 2 * eps + r2 * N * N / 2
+        t = model.cost(1.0 / N, N, width)
+        if best is None or t < best[0]:
+            best = (t, N)
+    return best[1]
+
+
+def split_sub(pieces: int, N: int, candidates: float, target_ns: float,
+              model: CostModel = MODEL, max_nu: int = 64):
+    """Split one sub-interval's pieces into items: list of (piece0, npieces, nu)."""
+    cost = model.cost(pieces, N, candidates)
+    n_items = max(1, min(pieces, int(round(cost / target_ns))))
+    n_items = max(n_items, -(-pieces // (64 * max_nu)))
+    per = -(-pieces // n_items)
+    out = []
+    p = 0
+    while p < pieces:
+        n = min(per, pieces - p)
+        out.append((p, n, -(-n // 64)))
+        p += n
+    return out

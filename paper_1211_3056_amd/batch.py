@@ -1,0 +1,245 @@
+"""Batched HR search: many jobs (functions, binades, sub-intervals of uneven
+piece length) as work items of one persistent launch.
+
+A job covers `count` consecutive binary64 arguments from X0.  It is cut
+into sub-intervals of `sub_len` arguments (the last one shorter if needed),
+each with its own piece length N (given per sub-interval, given once, or
+chosen by the autotuner) and a partial last piece when N does not divide
+the sub-interval.  Every sub-interval gets its table, window and thresholds
+from ``prep.SubPreparer``; its pieces are split into work items
+(``autotune.split_sub``).
+
+Two forms run the same kernel on the same items:
+  plain    one launch per job (one wave per item), results read back per job;
+  batched  one persistent launch over every item of every job (grouped by
+           word width and degree), items ordered by decreasing modelled cost.
+Both give identical result sets.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _lib, api, autotune
+from .prep import SubPreparer, is_hr, output_ulp_range, JobSpec
+
+M64 = 1 << 64
+
+
+@dataclass
+class BatchJob:
+    fname: str
+    X0: float
+    count: int
+    s: int
+    mode: str = "rn"
+    sub_len: int = 1 << 28
+    N: object = None          # int, list of ints (one per sub-interval), or None
+    delta: int | None = None
+    W: int | None = None
+    job_id: int = 0
+
+
+@dataclass
+class PlannedSub:
+    start: int
+    length: int
+    N: int
+
+    @property
+    def pieces(self) -> int:
+        return -(-self.length // self.N)
+
+
+@dataclass
+class PlannedJob:
+    job: BatchJob
+    delta: int
+    W: int
+    uf: object
+    subs: list = field(default_factory=list)
+
+
+def plan_job(job: BatchJob) -> PlannedJob:
+    uf = output_ulp_range(job.fname, job.X0, job.count)
+    n_sub = -(-job.count // job.sub_len)
+    if isinstance(job.N, (list, tuple, np.ndarray)):
+        Ns = [int(x) for x in job.N]
+        if len(Ns) != n_sub:
+            raise ValueError("one N per sub-interval expected")
+    else:
+        N = int(job.N) if job.N else autotune.choose_N(job.fname, job.X0, job.count, job.s, uf)
+        Ns = [N] * n_sub
+    subs = []
+    for t in range(n_sub):
+        start = t * job.sub_len
+        length = min(job.sub_len, job.count - start)
+        subs.append(PlannedSub(start, length, min(Ns[t], length)))
+    delta = job.delta or autotune.choose_degree(job.fname, job.X0, job.sub_len, job.s, uf)
+    W = job.W or autotune.choose_width([(s.N, s.pieces) for s in subs], delta, job.s)
+    for s in subs:
+        if s.pieces ** delta >= 1 << 128 or s.N ** delta >= 1 << 128:
+            raise ValueError("piece count or length too large for the degree")
+    return PlannedJob(job, delta, W, uf, subs)
+
+
+@dataclass
+class Plan:
+    jobs: list                # PlannedJob, in job order
+    pool: np.ndarray          # uint64 table pool
+    items: np.ndarray         # api.ITEM_DTYPE, grouped by job then sub (plain order)
+    variants: list            # (W, delta) of each item
+    prep_s: float = 0.0
+
+    def job_items(self, j: int):
+        return np.nonzero(self.items["job"] == j)[0]
+
+
+def build_plan(jobs, target_items: int = 16384, model=autotune.MODEL) -> Plan:
+    """Plan, prepare and split every job into work items."""
+    t0 = time.time()
+    planned = [plan_job(j) for j in jobs]
+    tables, item_rows, variants = [], [], []
+    offset = 0
+    total_cost = 0.0
+    staged = []
+    for pj in planned:
+        prep = SubPreparer(pj.job.fname, pj.job.X0, pj.job.s, pj.job.mode, pj.delta, pj.W, pj.uf)
+        for t, sp in enumerate(pj.subs):
+            table, win, thr = prep.prepare(sp.start, sp.length, sp.N)
+            cand = sp.length * float(win[1]) / 2.0 ** 64
+            cost = model.cost(sp.pieces, sp.N, cand)
+            total_cost += cost
+            staged.append((pj, t, sp, table, win, thr, cand, cost))
+    target = max(total_cost / target_items, 1e-9)
+    for pj, t, sp, table, win, thr, cand, cost in staged:
+        tables.append(table.reshape(-1))
+        last_piece = sp.pieces - 1 if sp.length % sp.N else 0xFFFFFFFF
+        last_N = sp.length - (sp.pieces - 1) * sp.N
+        for piece0, npieces, nu in autotune.split_sub(sp.pieces, sp.N, cand, target, model):
+            item_rows.append((offset, int(win[0]), int(win[1]), tuple(int(x) for x in thr),
+                              pj.job.job_id, t, piece0, npieces, nu, sp.N, last_piece, last_N))
+            variants.append((pj.W, pj.delta))
+        offset += table.size
+    items = np.array(item_rows, dtype=api.ITEM_DTYPE)
+    pool = np.concatenate(tables) if tables else np.zeros(1, np.uint64)
+    return Plan(planned, pool, items, variants, time.time() - t0)
+
+
+class DevicePlan:
+    """A plan resident in HBM: pool and items (plain and cost-sorted orders)."""
+
+    def __init__(self, plan: Plan, model=autotune.MODEL, device="cuda"):
+        self.plan = plan
+        self.pool = api.to_dev(plan.pool, torch.uint64, device)
+        raw = plan.items.view(np.uint8).reshape(-1)
+        self.items = api.to_dev(raw, torch.uint8, device)
+        # batched order: by variant, then decreasing modelled cost
+        cost = np.array([model.cost(it["npieces"], int(it["N"]),
+                                    float(it["win_d"]) / 2.0 ** 64 * int(it["npieces"]) * int(it["N"]))
+                         for it in plan.items])
+        var = np.array([v[0] * 16 + v[1] for v in plan.variants])
+        order = np.lexsort((-cost, var))
+        self.sorted_items = api.to_dev(plan.items[order].view(np.uint8).reshape(-1), torch.uint8, device)
+        self.groups = []          # (W, delta, first, count) over sorted_items
+        vs = var[order]
+        i = 0
+        while i < len(vs):
+            j = i
+            while j < len(vs) and vs[j] == vs[i]:
+                j += 1
+            W, d = plan.variants[order[i]]
+            self.groups.append((W, d, i, j - i))
+            i = j
+        self.job_groups = []      # per job: (W, delta, first, count) over plain items
+        for j, pj in enumerate(plan.jobs):
+            idx = plan.job_items(pj.job.job_id)
+            self.job_groups.append((pj.W, pj.delta, int(idx[0]), len(idx)) if len(idx) else None)
+
+
+def _run(ctx, dp, items_t, first, count_items, W, delta, waves, out, cap, count, stats, stream):
+    base = items_t[first * _lib.ITEM_BYTES:(first + count_items) * _lib.ITEM_BYTES]
+    _lib.hr_batch_run(ctx, dp.pool, base, count_items, W, delta, waves, out, cap, count, stats,
+                      stream)
+
+
+def device_waves() -> int:
+    props = torch.cuda.get_device_properties(0)
+    return props.multi_processor_count * 8
+
+
+class Runner:
+    """Owns output buffers; runs a DevicePlan in plain or batched form."""
+
+    def __init__(self, dp: DevicePlan, cap: int = 1 << 20, ctx=None):
+        self.dp = dp
+        self.ctx = ctx or api.context()
+        self.cap = cap
+        dev = dp.pool.device
+        self.out = torch.empty(cap * _lib.RESULT_BYTES, dtype=torch.uint8, device=dev)
+        self.count = torch.zeros(1, dtype=torch.uint64, device=dev)
+        self.stats = torch.zeros(4, dtype=torch.uint64, device=dev)
+
+    def _results(self):
+        n = api._u64_scalar(self.count)
+        if n > self.cap:
+            raise _lib.HRError("hr_batch_run", _lib.HR_ECAPACITY)
+        return self.out[: n * _lib.RESULT_BYTES].cpu().numpy().view(api.RESULT_DTYPE).copy()
+
+    def batched(self, waves: int | None = None, stream=None, sync=True):
+        """One persistent launch per (W, delta) group of the whole plan."""
+        waves = waves or device_waves()
+        self.count.zero_()
+        self.stats.zero_()
+        for W, d, first, n in self.dp.groups:
+            _run(self.ctx, self.dp, self.dp.sorted_items, first, n, W, d, waves, self.out,
+                 self.cap, self.count, self.stats, stream)
+        if not sync:
+            return None
+        torch.cuda.synchronize()
+        return self._results()
+
+    def plain(self, stream=None):
+        """One launch per job, each read back before the next one starts."""
+        self.stats.zero_()
+        parts = []
+        for g in self.dp.job_groups:
+            if g is None:
+                continue
+            W, d, first, n = g
+            self.count.zero_()
+            _run(self.ctx, self.dp, self.dp.items, first, n, W, d, 0, self.out, self.cap,
+                 self.count, self.stats, stream)
+            torch.cuda.synchronize()
+            parts.append(self._results())
+        return np.concatenate(parts) if parts else np.zeros(0, api.RESULT_DTYPE)
+
+    def stats_dict(self):
+        st = self.stats.cpu().numpy()
+        return {"pieces": int(st[0]), "candidates": int(st[1]), "results": int(st[2]),
+                "partial_quotients": int(st[3])}
+
+
+def finish(plan: Plan, results: np.ndarray):
+    """Per-job sorted HR offsets (argument X0 + m h), undecided values
+    decided at high precision on the host."""
+    by_id = {pj.job.job_id: pj for pj in plan.jobs}
+    out = {pj.job.job_id: [] for pj in plan.jobs}
+    for r in results:
+        pj = by_id[int(r["job"])]
+        sp = pj.subs[int(r["sub"])]
+        m = sp.start + int(r["piece"]) * sp.N + int(r["k"])
+        if int(r["cls"]) == 1:
+            out[pj.job.job_id].append(m)
+        elif int(r["cls"]) == 2:
+            spec = JobSpec(pj.job.fname, pj.job.X0, pj.job.count, pj.job.s, pj.job.mode)
+            if is_hr(spec, m, pj.uf):
+                out[pj.job.job_id].append(m)
+    return {k: sorted(v) for k, v in out.items()}
+
+
+def args_of(plan: Plan) -> int:
+    return sum(pj.job.count for pj in plan.jobs)

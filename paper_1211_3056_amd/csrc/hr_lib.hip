@@ -288,16 +288,126 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-// Fused pass over whole sub-intervals, one wave per workgroup.  Each lane
-// owns a packet of nu consecutive pieces of one sub-interval and keeps the
-// full difference table of all rows r_0..r_DEG in registers (packet start by
-// straightforward shift, then one tabulated-difference step per piece).
-// For its current piece a lane runs the exact degree-1 search; candidates
-// are compacted into an LDS queue (ballot + mbcnt) together with the
-// piece rows, and all 64 lanes then recheck queued candidates in parallel,
-// so that the uneven number of candidates per piece does not idle lanes.
 constexpr int kQueue = 512;
 
+// Where a queued candidate comes from: result identifiers and thresholds.
+struct Origin {
+    uint32_t job, sub, piece;
+    const uint64_t* thr;
+};
+
+// The per-wave body of the fused pass.  Each lane owns a packet of up to nu
+// consecutive pieces (cnt of them live, starting at piece p_begin) and keeps
+// the full difference table of all rows r_0..r_DEG in registers, advanced by
+// one tabulated-difference step per piece.  For its current piece a lane runs
+// the exact degree-1 search; candidates are compacted into an LDS queue
+// (ballot + mbcnt) next to the piece rows, and all 64 lanes then recheck
+// queued candidates in parallel, so the uneven number of candidates per
+// piece does not idle lanes.  origin(src, s) names the piece of lane src at
+// step s.  Must be called by the whole wave (uniform nu).
+template <int L, int DEG, class OriginFn>
+__device__ __forceinline__ void fused_wave(
+    hr::Word<L>* v, bool active, uint32_t cnt, uint32_t nu, uint64_t p_begin, uint32_t N,
+    uint32_t last_piece, uint32_t last_N, uint64_t wlo, uint64_t wd, uint32_t* s_rows,
+    uint32_t* s_qlane, uint32_t* s_qk, OriginFn&& origin, hr_result* __restrict__ out,
+    uint64_t cap, unsigned long long* __restrict__ count, uint64_t& n_pieces, uint64_t& n_cand,
+    uint64_t& n_res, uint64_t& n_steps) {
+    const int lane = threadIdx.x;
+    for (uint32_t s = 0; s < nu; ++s) {
+        const bool live = active && s < cnt;
+#pragma unroll
+        for (int j = 0; j <= DEG; ++j)
+#pragma unroll
+            for (int w = 0; w < L; ++w) s_rows[(j * L + w) * 64 + lane] = v[entry(DEG, j, 0)].w[w];
+        hr::HitIter it;
+        it.done = true;
+        if (live) {
+            uint32_t steps = 0;
+            const uint64_t piece = p_begin + s;
+            const uint32_t n = (piece == last_piece) ? last_N : N;
+            const uint64_t bb = top64(v[entry(DEG, 0, 0)]) - wlo;
+            const uint64_t aa = neg_top64(v[entry(DEG, 1, 0)]);
+            hr::iter_init(it, aa, bb, n, wd, &steps);
+            ++n_pieces;
+            n_steps += steps;
+        }
+        for (;;) {
+            uint32_t qn = 0;
+            for (;;) {   // fill: one hit per lane and round while room remains
+                uint64_t k = 0;
+                const bool has = hr::iter_next(it, k);
+                const uint64_t mask = __ballot(has);
+                if (has) {
+                    const uint32_t pos = qn + lanes_below(mask);
+                    s_qlane[pos] = (uint32_t)lane;
+                    s_qk[pos] = (uint32_t)k;
+                }
+                qn += (uint32_t)__popcll(mask);
+                if (mask == 0 || qn + 64 > kQueue) break;
+            }
+            __syncthreads();
+            for (uint32_t e = lane; e < qn; e += 64) {   // drain
+                const uint32_t src = s_qlane[e];
+                const uint64_t k = s_qk[e];
+                hr::Word<L> V;
+#pragma unroll
+                for (int w = 0; w < L; ++w) V.w[w] = s_rows[w * 64 + src];
+                uint32_t cb[DEG][4];
+                binom_limbs<DEG>(k, cb);
+#pragma unroll
+                for (int j = 1; j <= DEG; ++j) {
+                    hr::Word<L> r;
+#pragma unroll
+                    for (int w = 0; w < L; ++w) r.w[w] = s_rows[(j * L + w) * 64 + src];
+                    hr::wmac128(V, r, cb[j - 1]);
+                }
+                const uint64_t t = top64(V);
+                const Origin o = origin(src, s);
+                const uint8_t cls = classify<L>(t, o.thr);
+                if (cls) {
+                    const unsigned long long pos = atomicAdd(count, 1ull);
+                    if (pos < cap) {
+                        hr_result r;
+                        r.job = o.job;
+                        r.sub = o.sub;
+                        r.piece = o.piece;
+                        r.k = (uint32_t)k;
+                        r.cls = cls;
+                        r.reserved = 0;
+                        r.value = t;
+                        out[pos] = r;
+                    }
+                    ++n_res;
+                }
+                ++n_cand;
+            }
+            __syncthreads();
+            if (__ballot(!it.done) == 0) break;
+        }
+        static_for<0, DEG + 1>([&](auto J) {
+            constexpr int j = decltype(J)::value;
+            row_step<L, DEG - j + 1>(v + entry(DEG, j, 0));
+        });
+    }
+}
+
+__device__ __forceinline__ void flush_stats(unsigned long long* stats, uint64_t n_pieces,
+                                            uint64_t n_cand, uint64_t n_res, uint64_t n_steps) {
+    if (!stats) return;
+    n_pieces = wave_sum(n_pieces);
+    n_cand = wave_sum(n_cand);
+    n_res = wave_sum(n_res);
+    n_steps = wave_sum(n_steps);
+    if (threadIdx.x == 0) {
+        atomicAdd(stats + 0, (unsigned long long)n_pieces);
+        atomicAdd(stats + 1, (unsigned long long)n_cand);
+        atomicAdd(stats + 2, (unsigned long long)n_res);
+        atomicAdd(stats + 3, (unsigned long long)n_steps);
+    }
+}
+
+// Whole sub-intervals of one uniform job (hr_pipeline): lane gid owns packet
+// gid of the flattened (sub-interval, packet) grid.
 template <int L, int DEG>
 __global__ __launch_bounds__(64) void k_pipeline(
     const uint64_t* __restrict__ table, uint32_t n_sub, uint32_t tau, uint32_t nu, uint32_t N,
@@ -333,93 +443,85 @@ __global__ __launch_bounds__(64) void k_pipeline(
     const uint64_t wlo = active ? win[2 * sub] : 0;
     const uint64_t wd = active ? win[2 * sub + 1] : 0;
     uint64_t n_pieces = 0, n_cand = 0, n_res = 0, n_steps = 0;
-
-    for (uint32_t s = 0; s < nu; ++s) {
-        const bool live = active && s < cnt;
-#pragma unroll
-        for (int j = 0; j <= DEG; ++j)
-#pragma unroll
-            for (int w = 0; w < L; ++w) s_rows[(j * L + w) * 64 + lane] = v[entry(DEG, j, 0)].w[w];
-        hr::HitIter it;
-        it.done = true;
-        if (live) {
-            uint32_t steps = 0;
-            const uint64_t bb = top64(v[entry(DEG, 0, 0)]) - wlo;
-            const uint64_t aa = neg_top64(v[entry(DEG, 1, 0)]);
-            hr::iter_init(it, aa, bb, N, wd, &steps);
-            ++n_pieces;
-            n_steps += steps;
-        }
-        for (;;) {
-            uint32_t qn = 0;
-            for (;;) {   // fill: one hit per lane and round while room remains
-                uint64_t k = 0;
-                const bool has = hr::iter_next(it, k);
-                const uint64_t mask = __ballot(has);
-                if (has) {
-                    const uint32_t pos = qn + lanes_below(mask);
-                    s_qlane[pos] = (uint32_t)lane;
-                    s_qk[pos] = (uint32_t)k;
-                }
-                qn += (uint32_t)__popcll(mask);
-                if (mask == 0 || qn + 64 > kQueue) break;
-            }
-            __syncthreads();
-            for (uint32_t e = lane; e < qn; e += 64) {   // drain
-                const uint32_t src = s_qlane[e];
-                const uint64_t k = s_qk[e];
-                hr::Word<L> V;
-#pragma unroll
-                for (int w = 0; w < L; ++w) V.w[w] = s_rows[w * 64 + src];
-                uint32_t cb[DEG][4];
-                binom_limbs<DEG>(k, cb);
-#pragma unroll
-                for (int j = 1; j <= DEG; ++j) {
-                    hr::Word<L> r;
-#pragma unroll
-                    for (int w = 0; w < L; ++w) r.w[w] = s_rows[(j * L + w) * 64 + src];
-                    hr::wmac128(V, r, cb[j - 1]);
-                }
-                const uint64_t t = top64(V);
-                const uint64_t g = (uint64_t)blockIdx.x * 64 + src;
-                const uint64_t ssub = g / per_sub;
-                const uint8_t cls = classify<L>(t, thr + 4 * ssub);
-                if (cls) {
-                    const unsigned long long pos = atomicAdd(count, 1ull);
-                    if (pos < cap) {
-                        hr_result r;
-                        r.sub = (uint32_t)ssub;
-                        r.piece = (uint32_t)((g % per_sub) * nu + s);
-                        r.k = (uint32_t)k;
-                        r.cls = cls;
-                        r.value = t;
-                        out[pos] = r;
-                    }
-                    ++n_res;
-                }
-                ++n_cand;
-            }
-            __syncthreads();
-            if (__ballot(!it.done) == 0) break;
-        }
-        static_for<0, DEG + 1>([&](auto J) {
-            constexpr int j = decltype(J)::value;
-            row_step<L, DEG - j + 1>(v + entry(DEG, j, 0));
-        });
-    }
-    if (stats) {
-        n_pieces = wave_sum(n_pieces);
-        n_cand = wave_sum(n_cand);
-        n_res = wave_sum(n_res);
-        n_steps = wave_sum(n_steps);
-        if (lane == 0) {
-            atomicAdd(stats + 0, (unsigned long long)n_pieces);
-            atomicAdd(stats + 1, (unsigned long long)n_cand);
-            atomicAdd(stats + 2, (unsigned long long)n_res);
-            atomicAdd(stats + 3, (unsigned long long)n_steps);
-        }
-    }
+    auto origin = [&](uint32_t src, uint32_t s) {
+        const uint64_t g = (uint64_t)blockIdx.x * 64 + src;
+        const uint64_t ssub = g / per_sub;
+        Origin o;
+        o.job = 0;
+        o.sub = (uint32_t)ssub;
+        o.piece = (uint32_t)((g % per_sub) * nu + s);
+        o.thr = thr + 4 * ssub;
+        return o;
+    };
+    fused_wave<L, DEG>(v, active, cnt, nu, i0, N, 0xffffffffu, 0, wlo, wd, s_rows, s_qlane, s_qk,
+                       origin, out, cap, count, n_pieces, n_cand, n_res, n_steps);
+    flush_stats(stats, n_pieces, n_cand, n_res, n_steps);
 }
+
+// Work items of uneven size (hr_batch_run).  PERSIST: a fixed grid of waves
+// claims items from *next until the list is exhausted; otherwise workgroup
+// b processes item b.
+template <int L, int DEG, bool PERSIST>
+__global__ __launch_bounds__(64) void k_items(
+    const uint64_t* __restrict__ pool, const hr_item* __restrict__ items, uint32_t n_items,
+    unsigned int* __restrict__ next, hr_result* __restrict__ out, uint64_t cap,
+    unsigned long long* __restrict__ count, unsigned long long* __restrict__ stats) {
+    constexpr int E = n_entries(DEG);
+    __shared__ uint32_t s_rows[(DEG + 1) * L * 64];
+    __shared__ uint32_t s_qlane[kQueue];
+    __shared__ uint32_t s_qk[kQueue];
+    const int lane = threadIdx.x;
+    uint64_t n_pieces = 0, n_cand = 0, n_res = 0, n_steps = 0;
+    uint32_t idx;
+    if (PERSIST) {
+        uint32_t c = 0;
+        if (lane == 0) c = atomicAdd(next, 1u);
+        idx = __shfl(c, 0, 64);
+    } else {
+        idx = blockIdx.x;
+    }
+    while (idx < n_items) {
+        const hr_item* I = items + idx;
+        const uint32_t nu = I->nu;
+        const uint64_t p_begin = (uint64_t)I->piece0 + (uint64_t)lane * nu;
+        const uint64_t p_end = (uint64_t)I->piece0 + I->npieces;
+        const bool active = p_begin < p_end;
+        const uint32_t cnt = active ? (uint32_t)hr::umin(nu, p_end - p_begin) : 0;
+        hr::Word<L> v[E];
+        if (active) {
+            const uint64_t* T = pool + I->table;
+            uint32_t cb[DEG][4];
+            binom_limbs<DEG>(p_begin, cb);
+            static_for<0, DEG + 1>([&](auto J) {
+                row_start<L, DEG, decltype(J)::value>(T, cb, v + entry(DEG, decltype(J)::value, 0));
+            });
+        } else {
+#pragma unroll
+            for (int e = 0; e < E; ++e) hr::wzero(v[e]);
+        }
+        auto origin = [&](uint32_t src, uint32_t s) {
+            Origin o;
+            o.job = I->job;
+            o.sub = I->sub;
+            o.piece = I->piece0 + src * nu + s;
+            o.thr = I->thr;
+            return o;
+        };
+        fused_wave<L, DEG>(v, active, cnt, nu, p_begin, I->N, I->last_piece, I->last_N, I->win_lo,
+                           I->win_d, s_rows, s_qlane, s_qk, origin, out, cap, count, n_pieces,
+                           n_cand, n_res, n_steps);
+        if (PERSIST) {
+            uint32_t c = 0;
+            if (lane == 0) c = atomicAdd(next, 1u);
+            idx = __shfl(c, 0, 64);
+        } else {
+            idx = n_items;
+        }
+    }
+    flush_stats(stats, n_pieces, n_cand, n_res, n_steps);
+}
+
+__global__ void k_zero_u32(unsigned int* p) { *p = 0u; }
 
 // ---------------------------------------------------------------- host side
 
@@ -621,6 +723,35 @@ hr_status hr_pipeline(hr_ctx* ctx, const uint64_t* table, uint32_t n_sub, uint32
                 (k_pipeline<L_, D_><<<dim3((uint32_t)blocks), dim3(64), 0, st>>>(
                     table, n_sub, tau, nu, N, win, thr, out, cap,
                     (unsigned long long*)count, (unsigned long long*)stats)));
+    return launched();
+}
+
+hr_status hr_batch_run(hr_ctx* ctx, const uint64_t* pool, const hr_item* items, uint32_t n_items,
+                       uint32_t width_bits, uint32_t degree, uint32_t waves, hr_result* out,
+                       uint64_t cap, uint64_t* count, uint64_t* stats, void* stream) {
+    if (!ctx || !valid_poly(degree, width_bits) || !count) return HR_EINVAL;
+    if (n_items > 0x7fffffffu) return HR_EINVAL;
+    if (n_items == 0) return HR_OK;
+    if (!pool || !items || (cap > 0 && !out)) return HR_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return HR_EDEVICE;
+    hipStream_t st = as_stream(stream);
+    hr_status s = ensure_scratch(ctx, 256);
+    if (s != HR_OK) return s;
+    unsigned int* next = (unsigned int*)ctx->scratch;
+    unsigned long long* cnt = (unsigned long long*)count;
+    unsigned long long* sts = (unsigned long long*)stats;
+    if (waves > 0) {
+        k_zero_u32<<<1, 1, 0, st>>>(next);
+        if ((s = launched()) != HR_OK) return s;
+        const uint32_t grid = waves < n_items ? waves : n_items;
+        HR_DISPATCH(width_bits, degree,
+                    (k_items<L_, D_, true><<<dim3(grid), dim3(64), 0, st>>>(
+                        pool, items, n_items, next, out, cap, cnt, sts)));
+    } else {
+        HR_DISPATCH(width_bits, degree,
+                    (k_items<L_, D_, false><<<dim3(n_items), dim3(64), 0, st>>>(
+                        pool, items, n_items, next, out, cap, cnt, sts)));
+    }
     return launched();
 }
 

@@ -165,64 +165,85 @@ class Prepared:
     uf: mpf
 
 
-def output_ulp(spec: JobSpec) -> mpf:
+def output_ulp_range(fname: str, X0: float, count: int) -> mpf:
+    """ulp of f on [X0, X0 + count h); f must stay in one binade there."""
     with mpmath.workprec(128):
-        h = _ulp(spec.X0)
-        lo = _f(spec.fname, mpf(spec.X0))
-        hi = _f(spec.fname, mpf(spec.X0) + (spec.count - 1) * h)
+        h = _ulp(X0)
+        lo = _f(fname, mpf(X0))
+        hi = _f(fname, mpf(X0) + (count - 1) * h)
         e1, e2 = mpmath.frexp(lo)[1], mpmath.frexp(hi)[1]
         if e1 != e2 or lo <= 0:
-            raise ValueError(f"{spec.fname} leaves its output binade on this range")
+            raise ValueError(f"{fname} leaves its output binade on this range")
         return mpf(2) ** (e1 - 53)
 
 
-def prepare(spec: JobSpec, subs=None) -> Prepared:
-    """Tables, windows and thresholds for the given sub-intervals (default all)."""
-    if spec.fname not in FUNCTIONS:
-        raise ValueError(spec.fname)
-    if spec.W not in (128, 192, 256) or not 1 <= spec.delta <= 6:
-        raise ValueError("unsupported width or degree")
-    subs = np.arange(spec.n_sub, dtype=np.int64) if subs is None else np.asarray(subs, np.int64)
-    d, W, N, tau, L = spec.delta, spec.W, spec.N, spec.tau, spec.limbs
-    K = _k_matrices(N, d)
-    kmax = max(abs(v) for Kn in K for v in Kn.values())
-    G = kmax.bit_length() + 96
-    prec = W + G + 64
-    pairs = [(j, l) for j in range(d + 1) for l in range(d - j + 1)]
-    tables = np.zeros((len(subs), len(pairs), L), np.uint64)
-    win = np.zeros((len(subs), 2), np.uint64)
-    thr = np.zeros((len(subs), 4), np.uint64)
-    uf = output_ulp(spec)
-    with mpmath.workprec(prec):
-        h = _ulp(spec.X0)
-        eps = mpf(2) ** (-spec.s)
-        offset = eps - (mpf(1) / 2 if spec.mode == "rn" else 0)
-        scale = mpf(2) ** (W + G)
-        M = spec.per_sub
-        e_round = mpf(2) ** (-W) * sum(comb(N - 1, j) for j in range(d + 1)) \
-            * sum(comb(tau - 1, l) for l in range(d + 1))
-        e_row = mpf(2) ** (-W - 1) * sum(comb(tau - 1, l) for l in range(d + 1))
-        for row, t in enumerate(subs):
-            Xt = mpf(spec.X0) + int(t) * M * h
-            c = _taylor_coeffs(spec.fname, Xt, d, h, uf)
-            c[0] += offset
+def output_ulp(spec: JobSpec) -> mpf:
+    return output_ulp_range(spec.fname, spec.X0, spec.count)
+
+
+class SubPreparer:
+    """Tables, windows and thresholds of sub-intervals of one function range.
+
+    A sub-interval starts `start` arguments after X0, holds `length`
+    arguments and is cut into pieces of N arguments (the last one partial
+    when N does not divide length).  Its polynomial is the degree-delta
+    Taylor expansion at its first argument.
+    """
+
+    def __init__(self, fname: str, X0: float, s: int, mode: str, delta: int, W: int, uf):
+        if fname not in FUNCTIONS:
+            raise ValueError(fname)
+        if W not in (128, 192, 256) or not 1 <= delta <= 6:
+            raise ValueError("unsupported width or degree")
+        self.fname, self.X0, self.s, self.mode = fname, X0, s, mode
+        self.delta, self.W, self.uf = delta, W, uf
+        self.pairs = [(j, l) for j in range(delta + 1) for l in range(delta - j + 1)]
+        self._K = {}
+
+    def _kmat(self, N):
+        if N not in self._K:
+            K = _k_matrices(N, self.delta)
+            kmax = max(abs(v) for Kn in K for v in Kn.values())
+            self._K[N] = (K, kmax.bit_length() + 96)
+        return self._K[N]
+
+    def prepare(self, start: int, length: int, N: int):
+        """(table uint64 (E, L), window uint64 (2,), thresholds uint64 (4,))."""
+        d, W = self.delta, self.W
+        L = W // 64
+        tau = -(-length // N)
+        K, G = self._kmat(N)
+        table = np.zeros((len(self.pairs), L), np.uint64)
+        win = np.zeros(2, np.uint64)
+        thr = np.zeros(4, np.uint64)
+        with mpmath.workprec(W + G + 64):
+            h = _ulp(self.X0)
+            uf = self.uf
+            eps = mpf(2) ** (-self.s)
+            Xt = mpf(self.X0) + start * h
+            c = _taylor_coeffs(self.fname, Xt, d, h, uf)
+            c[0] += eps - (mpf(1) / 2 if self.mode == "rn" else 0)
+            scale = mpf(2) ** (W + G)
             C = [int(mpmath.nint(cn * scale)) for cn in c]
-            for e, (j, l) in enumerate(pairs):
+            for e, (j, l) in enumerate(self.pairs):
                 v = sum(C[n] * K[n][(j, l)] for n in range(d + 1))
                 v = ((v + (1 << (G - 1))) >> G) & ((1 << W) - 1)
                 for li in range(L):
-                    tables[row, e, li] = (v >> (64 * li)) & (M64 - 1)
+                    table[e, li] = (v >> (64 * li)) & (M64 - 1)
             # error budget of this sub-interval
+            M = length
+            e_round = mpf(2) ** (-W) * sum(comb(N - 1, j) for j in range(d + 1)) \
+                * sum(comb(tau - 1, l) for l in range(d + 1))
+            e_row = mpf(2) ** (-W - 1) * sum(comb(tau - 1, l) for l in range(d + 1))
             nA = d + 1
-            e_approx = _deriv_bound(spec.fname, Xt, Xt + M * h, nA) * (M * h) ** nA \
+            e_approx = _deriv_bound(self.fname, Xt, Xt + M * h, nA) * (M * h) ** nA \
                 / (mpmath.factorial(nA) * uf) * mpf("1.01")
             mu = e_approx + e_round
             # r_j(i) = Delta^j R(i N) lies in the range of R^(j) on [0, M + d]
             Y = mpf(M + d)
             t_lo = t_hi = mpf(0)
             for j in range(2, d + 1):
-                base = c[j] * mpmath.factorial(j)
-                lo_j = hi_j = base
+                lo_j = hi_j = c[j] * mpmath.factorial(j)
                 for n in range(j + 1, d + 1):
                     term = c[n] * mpmath.factorial(n) / mpmath.factorial(n - j) * Y ** (n - j)
                     lo_j += min(term, 0)
@@ -234,12 +255,27 @@ def prepare(spec: JobSpec, subs=None) -> Prepared:
             lo = -(mu + t_hi + one)
             width = 2 * eps + 2 * mu + (t_hi - t_lo) + (N + 1) * one
             s64 = mpf(2) ** 64
-            win[row, 0] = int(mpmath.floor(lo * s64)) % M64
-            win[row, 1] = min(int(mpmath.ceil(width * s64)) + 2, M64 - 1)
-            thr[row, 0] = int(mpmath.ceil(mu * s64))
-            thr[row, 1] = int(mpmath.floor((2 * eps - mu) * s64)) - 1
-            thr[row, 2] = int(mpmath.ceil((2 * eps + mu) * s64))
-            thr[row, 3] = int(mpmath.floor((1 - mu) * s64)) - 1
+            win[0] = int(mpmath.floor(lo * s64)) % M64
+            win[1] = min(int(mpmath.ceil(width * s64)) + 2, M64 - 1)
+            thr[0] = int(mpmath.ceil(mu * s64))
+            thr[1] = int(mpmath.floor((2 * eps - mu) * s64)) - 1
+            thr[2] = int(mpmath.ceil((2 * eps + mu) * s64))
+            thr[3] = int(mpmath.floor((1 - mu) * s64)) - 1
+        return table, win, thr
+
+
+def prepare(spec: JobSpec, subs=None) -> Prepared:
+    """Tables, windows and thresholds for the given sub-intervals (default all)."""
+    subs = np.arange(spec.n_sub, dtype=np.int64) if subs is None else np.asarray(subs, np.int64)
+    uf = output_ulp(spec)
+    sp = SubPreparer(spec.fname, spec.X0, spec.s, spec.mode, spec.delta, spec.W, uf)
+    tables = np.zeros((len(subs), spec.entries, spec.limbs), np.uint64)
+    win = np.zeros((len(subs), 2), np.uint64)
+    thr = np.zeros((len(subs), 4), np.uint64)
+    for row, t in enumerate(subs):
+        tables[row], win[row], thr[row] = sp.prepare(int(t) * spec.per_sub, spec.per_sub, spec.N)
+    with mpmath.workprec(64):
+        h = _ulp(spec.X0)
     return Prepared(spec, subs, tables, win, thr, h, uf)
 
 

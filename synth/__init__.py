@@ -71,3 +71,45 @@ def random_tables(seed: int, n_sub: int, delta: int, W: int):
     g = rng(seed)
     E = (delta + 1) * (delta + 2) // 2
     return g.integers(0, 2 ** 64, (n_sub, E, W // 64), dtype=np.uint64, endpoint=False)
+
+
+# Batched form: 16 jobs, 4 per function, slices of 2^30 .. 2^38 arguments
+# placed one after the other from each function's start, sub-intervals of
+# 2^28 arguments with piece lengths N uniform in [2^12, 2^20], eps = 2^-28 RN.
+CONFIG4 = dict(n_jobs=16, funcs=("exp", "log", "exp2", "sin"),
+               starts={"exp": 1.0, "exp2": 1.0, "sin": 1.0, "log": 3.0},
+               size_log2=(30, 38), N_range=(1 << 12, 1 << 20), s=28, sub_len=1 << 28, seed=4)
+
+
+def _ulp(x: float) -> float:
+    import math
+    return math.ldexp(1.0, math.frexp(x)[1] - 53)
+
+
+def config4(scale_log2: int = 0, N_scale_log2: int = 0, s: int | None = None, seed: int | None = None):
+    """Job descriptions (dicts) of the batched workload.
+
+    scale_log2 shrinks every slice and the sub-interval length by 2^scale_log2
+    and N_scale_log2 the piece lengths (smaller copies of the same mix, for
+    tests).  Job j is function funcs[j % 4]; its slice follows the previous
+    slices of the same function.
+    """
+    c = CONFIG4
+    g = rng(c["seed"] if seed is None else seed)
+    gN = rng(c["seed"] if seed is None else seed, 2)
+    lo, hi = c["size_log2"]
+    sizes = g.integers(lo, hi + 1, c["n_jobs"])
+    sub_len = c["sub_len"] >> scale_log2
+    Nlo, Nhi = c["N_range"][0] >> N_scale_log2, c["N_range"][1] >> N_scale_log2
+    used = {f: 0 for f in c["funcs"]}
+    jobs = []
+    for j in range(c["n_jobs"]):
+        f = c["funcs"][j % len(c["funcs"])]
+        count = 1 << (int(sizes[j]) - scale_log2)
+        X0 = c["starts"][f] + used[f] * _ulp(c["starts"][f])
+        used[f] += count
+        n_sub = -(-count // sub_len)
+        Ns = gN.integers(Nlo, Nhi, n_sub, endpoint=True).astype(int).tolist()
+        jobs.append(dict(fname=f, X0=X0, count=count, s=c["s"] if s is None else s, mode="rn",
+                         sub_len=sub_len, N=Ns, job_id=j))
+    return jobs

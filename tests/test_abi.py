@@ -40,5 +40,12 @@ def test_invalid_arguments_rejected_before_any_device_call():
     assert L.hr_destroy(None) == _lib.HR_OK
 
 
-def test_result_record_layout():
-    assert _lib.RESULT_BYTES == 24
+def test_record_layouts():
+    from paper_1211_3056_amd import api
+    assert _lib.RESULT_BYTES == 32 == api.RESULT_DTYPE.itemsize
+    assert _lib.ITEM_BYTES == 88 == api.ITEM_DTYPE.itemsize
+    # field offsets of the numpy views match the C structs
+    for name, _ in _lib.hr_item._fields_:
+        assert getattr(_lib.hr_item, name).offset == api.ITEM_DTYPE.fields[name][1]
+    for name, _ in _lib.hr_result._fields_:
+        assert getattr(_lib.hr_result, name).offset == api.RESULT_DTYPE.fields[name][1]

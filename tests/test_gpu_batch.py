@@ -1,0 +1,109 @@
+"""Batched persistent form: identical to the plain per-job form, and to the
+oracle on sampled jobs (uneven N per sub-interval, partial last pieces,
+mixed functions, word widths and degrees)."""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import synth
+from oracle import hr as ohr
+from oracle.taylor import Job
+
+pytestmark = pytest.mark.gpu
+
+
+def _ulp(x):
+    return math.ldexp(1.0, math.frexp(x)[1] - 53)
+
+
+def oracle_job(pj):
+    """Oracle HR offsets of a planned job, sub-interval by sub-interval: the
+    full pieces as one oracle job, the partial last piece as another."""
+    j = pj.job
+    h = _ulp(j.X0)
+    out = []
+    for sp in pj.subs:
+        Xt = j.X0 + sp.start * h
+        full, rem = divmod(sp.length, sp.N)
+        if full:
+            job = Job(j.fname, Xt, full * sp.N, j.s, j.mode, sp.N, full, pj.delta, pj.W)
+            out += [sp.start + m for m in ohr.pipeline(job)]
+        if rem:
+            job = Job(j.fname, Xt + full * sp.N * h, rem, j.s, j.mode, rem, 1, pj.delta, pj.W)
+            out += [sp.start + full * sp.N + m for m in ohr.pipeline(job)]
+    return sorted(out)
+
+
+def _sorted(res):
+    return np.sort(res, order=["job", "sub", "piece", "k"])
+
+
+def _scaled_jobs(**kw):
+    from paper_1211_3056_amd.batch import BatchJob
+    return [BatchJob(**d) for d in synth.config4(**kw)]
+
+
+def test_batched_equals_plain_and_oracle():
+    from paper_1211_3056_amd import batch
+    jobs = _scaled_jobs(scale_log2=16, N_scale_log2=8, s=12)
+    plan = batch.build_plan(jobs, target_items=2048)
+    dp = batch.DevicePlan(plan)
+    run = batch.Runner(dp)
+    plain = _sorted(run.plain())
+    st_plain = run.stats_dict()
+    batched = _sorted(run.batched())
+    st_b = run.stats_dict()
+    assert plain.tobytes() == batched.tobytes()
+    assert st_plain["candidates"] == st_b["candidates"] > 0
+    assert st_plain["pieces"] == st_b["pieces"] == sum(sp.pieces for pj in plan.jobs for sp in pj.subs)
+    hr = batch.finish(plan, batched)
+    # log near 3 advances by exactly 2/3 ulp per argument: its values sit on
+    # a 3-point lattice mod 1 and its HR count is not Poisson; the others are
+    total = sum(len(hr[pj.job.job_id]) for pj in plan.jobs if pj.job.fname != "log")
+    expect = 2 * 2 ** -12 * sum(pj.job.count for pj in plan.jobs if pj.job.fname != "log")
+    assert 0.8 * expect < total < 1.2 * expect
+    # the smallest job of each function against the oracle
+    smallest = {}
+    for pj in plan.jobs:
+        f = pj.job.fname
+        if f not in smallest or pj.job.count < smallest[f].job.count:
+            smallest[f] = pj
+    for f, pj in smallest.items():
+        assert hr[pj.job.job_id] == oracle_job(pj), f
+
+
+def test_persistent_queue_with_few_waves_and_repeats():
+    """Fewer waves than items (each wave loops over the claim counter), run
+    twice in a row: same bytes every time."""
+    from paper_1211_3056_amd import batch
+    jobs = _scaled_jobs(scale_log2=17, N_scale_log2=8, s=14)
+    dp = batch.DevicePlan(batch.build_plan(jobs, target_items=1024))
+    run = batch.Runner(dp)
+    ref = _sorted(run.batched(waves=7))
+    for waves in (1, 64, None):
+        assert _sorted(run.batched(waves=waves)).tobytes() == ref.tobytes()
+
+
+def test_mixed_widths_degrees_and_ragged_ranges():
+    from paper_1211_3056_amd import batch
+    from paper_1211_3056_amd.batch import BatchJob
+    jobs = [
+        BatchJob("exp", 1.0, 300_001, 11, "rn", sub_len=65_536, N=[1000, 777, 4096, 333, 5000], W=192, delta=4, job_id=0),
+        BatchJob("sin", 1.25, 200_000, 11, "dir", sub_len=50_000, N=1 << 9, W=128, delta=3, job_id=1),
+        BatchJob("log", 3.5, 131_072, 11, "rn", sub_len=1 << 15, N=None, job_id=2),
+        BatchJob("exp2", 1.5, 99_999, 11, "rn", sub_len=1 << 14, N=100, W=256, delta=2, job_id=3),
+        BatchJob("cos", 1.0, 65_536, 11, "rn", sub_len=1 << 16, N=1 << 8, job_id=4),
+    ]
+    plan = batch.build_plan(jobs, target_items=512)
+    dp = batch.DevicePlan(plan)
+    assert len(dp.groups) >= 3
+    run = batch.Runner(dp)
+    b = _sorted(run.batched())
+    p = _sorted(run.plain())
+    assert b.tobytes() == p.tobytes()
+    hr = batch.finish(plan, b)
+    for pj in plan.jobs:
+        assert hr[pj.job.job_id] == oracle_job(pj), pj.job.fname
