@@ -36,6 +36,9 @@ def parse():
     p.add_argument("--cpu-subs", type=int, default=16,
                    help="sub-intervals in the oracle's timed sample")
     p.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain workload")
+    p.add_argument("--no-serve", action="store_true", help="skip the serving workload")
+    p.add_argument("--serve-jobs", type=int, default=2000)
+    p.add_argument("--prep-workers", type=int, default=16)
     return p.parse_args()
 
 
@@ -59,6 +62,11 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); every "
               "box in this setup has a single MI355X", file=sys.stderr)
         sys.exit(2)
+    pool = None
+    if not args.no_serve:
+        # preparation workers come from a forkserver started before the GPU is used
+        from paper_1211_3056_amd import serve
+        pool = serve.make_pool(args.prep_workers)
     import numpy as np
     import torch
 
@@ -156,6 +164,8 @@ def main():
                               "hr_cases": len(hr_plain)}
     if not args.no_batch:
         line["batch"] = bench_batch(args)
+    if not args.no_serve:
+        line["serving"] = bench_serve(args, pool)
     if not args.no_cpu_baseline:
         from oracle import hr as ohr
         from oracle import native
@@ -216,6 +226,40 @@ def bench_batch(args):
             "speedup": p_s / b_s, "identical_results": bool(same),
             "hr_cases": sum(len(v) for v in hr.values()), "candidates": st["candidates"],
             "host_prep_s": plan.prep_s}
+
+
+def bench_serve(args, pool):
+    """2000 jobs (five functions, 2^24..2^36 arguments, eps 2^-20 or 2^-28):
+    capacity with every job present at t = 0, then Poisson arrivals at 0.8 x
+    that capacity; p50 / p99 latency from arrival to result."""
+    import numpy as np
+
+    import synth
+    from paper_1211_3056_amd import serve
+    from paper_1211_3056_amd.plan import BatchJob
+
+    jobs = [BatchJob(**d) for d in synth.config5(n_jobs=args.serve_jobs)]
+    be = serve.GpuBackend()
+    srv = serve.Server(be, pool)
+    t0 = time.perf_counter()
+    sat = srv.serve(jobs, np.zeros(len(jobs)), realtime=False)
+    cap_s = time.perf_counter() - t0
+    capacity = sum(s.status == "done" for s in sat) / cap_s
+    rate = 0.8 * capacity
+    arrivals = synth.poisson_arrivals(len(jobs), rate)
+    srv = serve.Server(be, pool)
+    steps0 = be.steps
+    t0 = time.perf_counter()
+    states = srv.serve(jobs, arrivals)
+    span = time.perf_counter() - t0
+    summ = serve.summarize(states, span)
+    summ.update({"workload": f"{len(jobs)} jobs, exp/log/2^x/sin/cos, 2^24..2^36 args "
+                             "(log-uniform), eps 2^-20 or 2^-28 RN, Poisson arrivals",
+                 "capacity_jobs_per_s": capacity, "arrival_rate_jobs_per_s": rate,
+                 "device_steps": be.steps - steps0, "prep_workers": args.prep_workers,
+                 "hbm_budget_bytes": srv.budget, "peak_hbm_bytes": srv.peak_used,
+                 "same_hr_as_saturated_run": all(a.hr == b.hr for a, b in zip(sat, states))})
+    return summ
 
 
 if __name__ == "__main__":

@@ -85,13 +85,7 @@ def recheck(table, n_sub, degree, tau, width, cand_inst, cand_k, max_k, thr, ctx
     return value[:n], cls[:n]
 
 
-RESULT_DTYPE = np.dtype([("job", np.uint32), ("sub", np.uint32), ("piece", np.uint32),
-                         ("k", np.uint32), ("cls", np.uint32), ("reserved", np.uint32),
-                         ("value", np.uint64)])
-ITEM_DTYPE = np.dtype([("table", np.uint64), ("win_lo", np.uint64), ("win_d", np.uint64),
-                       ("thr", np.uint64, (4,)), ("job", np.uint32), ("sub", np.uint32),
-                       ("piece0", np.uint32), ("npieces", np.uint32), ("nu", np.uint32),
-                       ("N", np.uint32), ("last_piece", np.uint32), ("last_N", np.uint32)])
+from .plan import ITEM_DTYPE, RESULT_DTYPE  # noqa: E402,F401
 
 
 def pipeline(table, n_sub, degree, tau, width, N, win, thr, cap=1 << 16, ctx=None, stream=None):

@@ -18,72 +18,16 @@ Both give identical result sets.
 from __future__ import annotations
 
 import time
-from dataclasses import dataclass, field
+from dataclasses import dataclass
 
 import numpy as np
 import torch
 
 from . import _lib, api, autotune
-from .prep import SubPreparer, is_hr, output_ulp_range, JobSpec
+from .plan import BatchJob, PlannedJob, PlannedSub, plan_job  # noqa: F401
+from .prep import JobSpec, SubPreparer, is_hr
 
 M64 = 1 << 64
-
-
-@dataclass
-class BatchJob:
-    fname: str
-    X0: float
-    count: int
-    s: int
-    mode: str = "rn"
-    sub_len: int = 1 << 28
-    N: object = None          # int, list of ints (one per sub-interval), or None
-    delta: int | None = None
-    W: int | None = None
-    job_id: int = 0
-
-
-@dataclass
-class PlannedSub:
-    start: int
-    length: int
-    N: int
-
-    @property
-    def pieces(self) -> int:
-        return -(-self.length // self.N)
-
-
-@dataclass
-class PlannedJob:
-    job: BatchJob
-    delta: int
-    W: int
-    uf: object
-    subs: list = field(default_factory=list)
-
-
-def plan_job(job: BatchJob) -> PlannedJob:
-    uf = output_ulp_range(job.fname, job.X0, job.count)
-    n_sub = -(-job.count // job.sub_len)
-    if isinstance(job.N, (list, tuple, np.ndarray)):
-        Ns = [int(x) for x in job.N]
-        if len(Ns) != n_sub:
-            raise ValueError("one N per sub-interval expected")
-    else:
-        N = int(job.N) if job.N else autotune.choose_N(job.fname, job.X0, job.count, job.s, uf)
-        Ns = [N] * n_sub
-    subs = []
-    for t in range(n_sub):
-        start = t * job.sub_len
-        length = min(job.sub_len, job.count - start)
-        subs.append(PlannedSub(start, length, min(Ns[t], length)))
-    delta = job.delta or autotune.choose_degree(job.fname, job.X0, job.sub_len, job.s, uf)
-    W = job.W or autotune.choose_width([(s.N, s.pieces) for s in subs], delta, job.s)
-    for s in subs:
-        if s.pieces ** delta >= 1 << 128 or s.N ** delta >= 1 << 128:
-            raise ValueError("piece count or length too large for the degree")
-    return PlannedJob(job, delta, W, uf, subs)
 
 
 @dataclass
@@ -189,18 +133,27 @@ class Runner:
             raise _lib.HRError("hr_batch_run", _lib.HR_ECAPACITY)
         return self.out[: n * _lib.RESULT_BYTES].cpu().numpy().view(api.RESULT_DTYPE).copy()
 
+    def _grow(self, n):
+        self.cap = 1 << (n - 1).bit_length()
+        self.out = torch.empty(self.cap * _lib.RESULT_BYTES, dtype=torch.uint8,
+                               device=self.dp.pool.device)
+
     def batched(self, waves: int | None = None, stream=None, sync=True):
         """One persistent launch per (W, delta) group of the whole plan."""
         waves = waves or device_waves()
-        self.count.zero_()
-        self.stats.zero_()
-        for W, d, first, n in self.dp.groups:
-            _run(self.ctx, self.dp, self.dp.sorted_items, first, n, W, d, waves, self.out,
-                 self.cap, self.count, self.stats, stream)
-        if not sync:
-            return None
-        torch.cuda.synchronize()
-        return self._results()
+        while True:
+            self.count.zero_()
+            self.stats.zero_()
+            for W, d, first, n in self.dp.groups:
+                _run(self.ctx, self.dp, self.dp.sorted_items, first, n, W, d, waves, self.out,
+                     self.cap, self.count, self.stats, stream)
+            if not sync:
+                return None
+            torch.cuda.synchronize()
+            n = api._u64_scalar(self.count)
+            if n <= self.cap:
+                return self._results()
+            self._grow(n)
 
     def plain(self, stream=None):
         """One launch per job, each read back before the next one starts."""
@@ -209,11 +162,18 @@ class Runner:
         for g in self.dp.job_groups:
             if g is None:
                 continue
-            W, d, first, n = g
-            self.count.zero_()
-            _run(self.ctx, self.dp, self.dp.items, first, n, W, d, 0, self.out, self.cap,
-                 self.count, self.stats, stream)
-            torch.cuda.synchronize()
+            W, d, first, n_items = g
+            before = self.stats.clone()
+            while True:
+                self.count.zero_()
+                self.stats.copy_(before)
+                _run(self.ctx, self.dp, self.dp.items, first, n_items, W, d, 0, self.out,
+                     self.cap, self.count, self.stats, stream)
+                torch.cuda.synchronize()
+                n = api._u64_scalar(self.count)
+                if n <= self.cap:
+                    break
+                self._grow(n)
             parts.append(self._results())
         return np.concatenate(parts) if parts else np.zeros(0, api.RESULT_DTYPE)
 
@@ -226,19 +186,21 @@ class Runner:
 def finish(plan: Plan, results: np.ndarray):
     """Per-job sorted HR offsets (argument X0 + m h), undecided values
     decided at high precision on the host."""
-    by_id = {pj.job.job_id: pj for pj in plan.jobs}
-    out = {pj.job.job_id: [] for pj in plan.jobs}
-    for r in results:
-        pj = by_id[int(r["job"])]
-        sp = pj.subs[int(r["sub"])]
-        m = sp.start + int(r["piece"]) * sp.N + int(r["k"])
-        if int(r["cls"]) == 1:
-            out[pj.job.job_id].append(m)
-        elif int(r["cls"]) == 2:
+    out = {}
+    for pj in plan.jobs:
+        jid = pj.job.job_id
+        res = results[results["job"] == jid]
+        starts = np.array([sp.start for sp in pj.subs], dtype=np.int64)
+        Ns = np.array([sp.N for sp in pj.subs], dtype=np.int64)
+        sub = res["sub"].astype(np.int64)
+        m = starts[sub] + res["piece"].astype(np.int64) * Ns[sub] + res["k"].astype(np.int64)
+        hr = m[res["cls"] == 1].tolist()
+        und = m[res["cls"] == 2].tolist()
+        if und:
             spec = JobSpec(pj.job.fname, pj.job.X0, pj.job.count, pj.job.s, pj.job.mode)
-            if is_hr(spec, m, pj.uf):
-                out[pj.job.job_id].append(m)
-    return {k: sorted(v) for k, v in out.items()}
+            hr += [x for x in und if is_hr(spec, x, pj.uf)]
+        out[jid] = sorted(hr)
+    return out
 
 
 def args_of(plan: Plan) -> int:

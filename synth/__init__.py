@@ -113,3 +113,42 @@ def config4(scale_log2: int = 0, N_scale_log2: int = 0, s: int | None = None, se
         jobs.append(dict(fname=f, X0=X0, count=count, s=c["s"] if s is None else s, mode="rn",
                          sub_len=sub_len, N=Ns, job_id=j))
     return jobs
+
+
+# Serving: 2000 jobs, Poisson arrivals; f uniform over five functions, sizes
+# round(2^U) with U ~ U(24, 36), eps 2^-20 or 2^-28, starts seeded and aligned
+# to 2^24 arguments inside each function's one-binade region.
+CONFIG5 = dict(n_jobs=2000, funcs=("exp", "log", "exp2", "sin", "cos"),
+               starts={"exp": 1.0, "log": 3.0, "exp2": 1.0, "sin": 1.0, "cos": 1.0},
+               # arguments available from the start with f in one output binade:
+               # exp < ln 4, log < 4, 2^x < 2, sin < pi/2, cos > 1/2 (x < pi/3)
+               room={"exp": 0.3862943611198906, "log": 1.0, "exp2": 1.0,
+                     "sin": 0.5707963267948966, "cos": 0.0471975511965976},
+               size_log2=(24.0, 36.0), s_choices=(20, 28), align=1 << 24, seed=5)
+
+
+def config5(n_jobs: int | None = None, size_log2=None, seed: int | None = None):
+    """Job descriptions (dicts) of the serving workload, in arrival order."""
+    import math
+    c = CONFIG5
+    n = c["n_jobs"] if n_jobs is None else n_jobs
+    lo, hi = c["size_log2"] if size_log2 is None else size_log2
+    g = rng(c["seed"] if seed is None else seed)
+    jobs = []
+    for j in range(n):
+        f = c["funcs"][int(g.integers(0, len(c["funcs"])))]
+        size = int(round(2.0 ** g.uniform(lo, hi)))
+        s = int(c["s_choices"][int(g.integers(0, len(c["s_choices"])))])
+        h = _ulp(c["starts"][f])
+        room_args = int(c["room"][f] / h) - size - 1
+        slots = max(1, room_args // c["align"])
+        off = int(g.integers(0, slots)) * c["align"]
+        X0 = c["starts"][f] + off * h
+        jobs.append(dict(fname=f, X0=X0, count=size, s=s, mode="rn", job_id=j))
+    return jobs
+
+
+def poisson_arrivals(n: int, rate: float, seed: int = 5) -> np.ndarray:
+    """Arrival times (s) of a Poisson process with the given rate (jobs/s)."""
+    g = rng(seed, 2)
+    return np.cumsum(g.exponential(1.0 / rate, n))

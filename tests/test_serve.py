@@ -1,0 +1,108 @@
+"""Serving loop logic on the CPU with a stand-in device backend: admission
+by footprint, slots, FIFO order, failure isolation, latency bookkeeping."""
+import numpy as np
+import pytest
+
+from paper_1211_3056_amd import serve
+from paper_1211_3056_amd.plan import RESULT_DTYPE, BatchJob
+
+
+class FakeBackend:
+    """Runs nothing; records which jobs each step carried."""
+
+    def __init__(self, free=1 << 30, fail_on=None):
+        self.free = free
+        self.steps = []
+        self.fail_on = fail_on
+        self.resident = set()
+        self.max_resident = 0
+
+    def free_memory(self):
+        return self.free
+
+    def admit(self, st):
+        self.resident.add(st.job.job_id)
+        self.max_resident = max(self.max_resident, len(self.resident))
+
+    def release(self, st):
+        self.resident.discard(st.job.job_id)
+
+    def step(self, states):
+        ids = [s.job.job_id for s in states]
+        self.steps.append(ids)
+        if self.fail_on is not None and self.fail_on in ids:
+            raise RuntimeError("device step failed")
+        return [np.zeros(0, RESULT_DTYPE) for _ in states]
+
+
+@pytest.fixture(scope="module")
+def pool():
+    p = serve.make_pool(2)
+    yield p
+    p.shutdown()
+
+
+def _jobs(n, size=1 << 16):
+    return [BatchJob("exp", 1.0 + 0.001 * i, size, 20, "rn", N=1 << 10, job_id=i) for i in range(n)]
+
+
+def test_all_jobs_complete_in_arrival_order(pool):
+    be = FakeBackend()
+    jobs = _jobs(8)
+    arrivals = np.linspace(0, 0.05, 8)
+    states = serve.Server(be, pool, hbm_budget=1 << 30).serve(jobs, arrivals)
+    assert [s.status for s in states] == ["done"] * 8
+    assert all(s.latency >= 0 and s.t_admit >= s.arrival for s in states)
+    seen = [i for step in be.steps for i in step]
+    assert sorted(seen) == list(range(8))
+
+
+def test_small_budget_blocks_admission(pool):
+    be = FakeBackend()
+    jobs = _jobs(6)
+    fp = serve.prepare_job(jobs[0]).footprint
+    srv = serve.Server(be, pool, hbm_budget=int(fp * 1.5))
+    states = srv.serve(jobs, np.zeros(6), realtime=False)
+    assert all(s.status == "done" for s in states)
+    assert be.max_resident == 1          # only one job fits at a time
+    assert srv.peak_used <= srv.budget
+    assert srv.blocked_admissions > 0
+    assert len(be.steps) == 6
+
+
+def test_slot_cap(pool):
+    be = FakeBackend()
+    srv = serve.Server(be, pool, hbm_budget=1 << 30, max_resident=2)
+    states = srv.serve(_jobs(5), np.zeros(5), realtime=False)
+    assert all(s.status == "done" for s in states)
+    assert max(len(s) for s in be.steps) <= 2
+
+
+def test_failures_are_isolated(pool):
+    be = FakeBackend()
+    jobs = _jobs(4)
+    # exp crosses 4 near ln 4: preparation refuses this range
+    jobs.append(BatchJob("exp", 1.3862943, 1 << 40, 20, "rn", N=1 << 10, job_id=4))
+    # larger than the budget
+    jobs.append(BatchJob("exp", 1.1, 1 << 33, 20, "rn", N=1 << 10, job_id=5))
+    fp = serve.prepare_job(jobs[0]).footprint
+    srv = serve.Server(be, pool, hbm_budget=fp * 3)
+    states = srv.serve(jobs, np.zeros(len(jobs)), realtime=False)
+    st = {s.job.job_id: s for s in states}
+    assert st[4].status == "failed" and "binade" in st[4].error
+    assert st[5].status == "failed" and "budget" in st[5].error
+    assert all(st[i].status == "done" for i in range(4))
+
+
+def test_device_failure_fails_only_that_step(pool):
+    be = FakeBackend(fail_on=2)
+    srv = serve.Server(be, pool, hbm_budget=1 << 30, max_resident=1)
+    states = srv.serve(_jobs(4), np.zeros(4), realtime=False)
+    assert [s.status for s in states] == ["done", "done", "failed", "done"]
+
+
+def test_summary_fields(pool):
+    be = FakeBackend()
+    states = serve.Server(be, pool, hbm_budget=1 << 30).serve(_jobs(3), np.zeros(3))
+    s = serve.summarize(states)
+    assert s["done"] == 3 and s["jobs_per_s"] > 0 and s["p99_latency_ms"] >= s["p50_latency_ms"]
