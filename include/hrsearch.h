@@ -214,6 +214,16 @@ hr_status hr_batch_run(hr_ctx* ctx, const uint64_t* pool, const hr_item* items, 
                        uint32_t width_bits, uint32_t degree, uint32_t waves, hr_result* out,
                        uint64_t cap, uint64_t* count, uint64_t* stats, void* stream);
 
+/*
+ * hr_quot_check -- diagnostic: the partial-quotient routine of the search,
+ * out[i] = min(floor(num[i] / den[i]), cap) computed by the device code
+ * (binary64 estimate + exact correction); out[i] = 2^64 - 1 where den[i] = 0.
+ * For checking that routine against exact integer division.
+ * Errors: HR_EINVAL for cap == 0 or cap >= 2^32, or null pointers.
+ */
+hr_status hr_quot_check(hr_ctx* ctx, const uint64_t* num, const uint64_t* den, uint64_t cap,
+                        uint64_t* out, uint64_t n, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -43,7 +43,7 @@ class hr_item(ctypes.Structure):
 RESULT_BYTES = ctypes.sizeof(hr_result)
 ITEM_BYTES = ctypes.sizeof(hr_item)
 EXPORTS = ("hr_abi_version", "hr_status_str", "hr_create", "hr_destroy", "hr_search", "hr_batch_run",
-           "hr_tabulate", "hr_recheck", "hr_pipeline")
+           "hr_tabulate", "hr_recheck", "hr_pipeline", "hr_quot_check")
 
 
 def lib():
@@ -71,6 +71,8 @@ def lib():
     L.hr_recheck.argtypes = [P, P, u32, u32, u32, u32, P, P, u64, u32, P, P, P, P]
     L.hr_pipeline.restype = i32
     L.hr_pipeline.argtypes = [P, P, u32, u32, u32, u32, u32, P, P, P, u64, P, P, P]
+    L.hr_quot_check.restype = i32
+    L.hr_quot_check.argtypes = [P, P, P, u64, P, u64, P]
     L.hr_batch_run.restype = i32
     L.hr_batch_run.argtypes = [P, P, P, u32, u32, u32, u32, P, u64, P, P, P]
     _lib = L
@@ -154,3 +156,8 @@ def hr_batch_run(ctx, pool, items, n_items, width, degree, waves, out, cap, coun
     _check("hr_batch_run", lib().hr_batch_run(ctx.handle, _p(pool), _p(items), n_items, width,
                                               degree, waves, _p(out), cap, _p(count), _p(stats),
                                               _stream(stream)))
+
+
+def hr_quot_check(ctx, num, den, cap, out, stream=None):
+    _check("hr_quot_check", lib().hr_quot_check(ctx.handle, _p(num), _p(den), cap, _p(out),
+                                                num.numel(), _stream(stream)))

@@ -23,15 +23,29 @@ HR_HD uint64_t mulhi64(uint64_t a, uint64_t b) {
 
 HR_HD uint64_t umin(uint64_t a, uint64_t b) { return a < b ? a : b; }
 
-// min(floor(num / den), cap) for den > 0, cap < 2^40.
-// The binary64 quotient of the two (rounded) operands is within 2^-10 of
-// the true quotient whenever it is below cap + 2, so its floor is off by at
-// most one; one exact multiply-compare corrects it.  Larger quotients
-// saturate at cap: callers only need to know that they reach cap.
+// Quotient estimate num/den in binary64 with relative error below 2^-50:
+// on the device one reciprocal (v_rcp_f64) refined by one Newton step, on
+// the host an IEEE division.
+HR_HD double fdiv_est(double num, double den) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    double r = __builtin_amdgcn_rcp(den);
+    const double e = __builtin_fma(-den, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    return num * r;
+#else
+    return num / den;
+#endif
+}
+
+// min(floor(num / den), cap) for den > 0, cap < 2^32.
+// The binary64 estimate of the quotient of the (rounded) operands is within
+// 2^-10 of the true quotient whenever it is below cap + 2, so its floor is
+// off by at most one; one exact multiply-compare corrects it.  Larger
+// quotients saturate at cap: callers only need to know that they reach cap.
 HR_HD uint64_t quot_sat(uint64_t num, uint64_t den, uint64_t cap) {
-    const double e = (double)num / (double)den;
+    const double e = fdiv_est((double)num, (double)den);
     if (e > (double)cap + 2.0) return cap;
-    uint64_t k = (uint64_t)e;
+    uint64_t k = (uint64_t)(uint32_t)__builtin_fmin(e, 4294967295.0);
     const uint64_t lo = k * den;
     if (mulhi64(k, den) != 0 || lo > num) {
         k -= 1;
@@ -39,6 +53,12 @@ HR_HD uint64_t quot_sat(uint64_t num, uint64_t den, uint64_t cap) {
         k += 1;
     }
     return k < cap ? k : cap;
+}
+
+// floor(a / b) for 0 <= a < 2^53, 0 < b < 2^53 (indices): the correctly
+// rounded binary64 quotient is never within rounding of the next integer.
+HR_HD uint64_t idx_div(uint64_t a, uint64_t b) {
+    return (uint64_t)__builtin_floor((double)a / (double)b);
 }
 
 // ----------------------------------------------------------------------
@@ -100,12 +120,12 @@ HR_HD void closest_left(uint64_t a, uint64_t b, uint64_t n, Near& r) {
             if (p < q) {
                 k = quot_sat(q, p, n);
                 if (X >= iq) {   // b inside a q-interval: it is split at p, 2p, ..
-                    const uint64_t s = umin(umin(quot_sat(d, p, n), k), (n - 1 - X) / ip);
+                    const uint64_t s = umin(umin(quot_sat(d, p, n), k), idx_div(n - 1 - X, ip));
                     X += s * ip;
                     d -= s * p;
                 }
                 if (ip + iq + k * ip >= n) {
-                    const uint64_t sv = umin(k, (n - 1 - iq) / ip);
+                    const uint64_t sv = umin(k, idx_div(n - 1 - iq, ip));
                     u = ip;
                     alpha = p;
                     v = iq + sv * ip;
@@ -125,7 +145,7 @@ HR_HD void closest_left(uint64_t a, uint64_t b, uint64_t n, Near& r) {
                     }
                 }
                 if (ip + iq + k * iq >= n) {
-                    const uint64_t su = umin(k, (n - 1 - ip) / iq);
+                    const uint64_t su = umin(k, idx_div(n - 1 - ip, iq));
                     v = iq;
                     beta = q;
                     u = ip + su * iq;

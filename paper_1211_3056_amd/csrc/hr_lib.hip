@@ -523,6 +523,14 @@ __global__ __launch_bounds__(64) void k_items(
 
 __global__ void k_zero_u32(unsigned int* p) { *p = 0u; }
 
+__global__ __launch_bounds__(kBlock) void k_quot_check(const uint64_t* __restrict__ num,
+                                                      const uint64_t* __restrict__ den,
+                                                      uint64_t cap, uint64_t* __restrict__ out,
+                                                      uint64_t n) {
+    const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) out[i] = den[i] ? hr::quot_sat(num[i], den[i], cap) : ~0ull;
+}
+
 // ---------------------------------------------------------------- host side
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
@@ -723,6 +731,19 @@ hr_status hr_pipeline(hr_ctx* ctx, const uint64_t* table, uint32_t n_sub, uint32
                 (k_pipeline<L_, D_><<<dim3((uint32_t)blocks), dim3(64), 0, st>>>(
                     table, n_sub, tau, nu, N, win, thr, out, cap,
                     (unsigned long long*)count, (unsigned long long*)stats)));
+    return launched();
+}
+
+hr_status hr_quot_check(hr_ctx* ctx, const uint64_t* num, const uint64_t* den, uint64_t cap,
+                        uint64_t* out, uint64_t n, void* stream) {
+    if (!ctx || cap == 0 || cap >= (1ull << 32)) return HR_EINVAL;
+    if (n == 0) return HR_OK;
+    if (!num || !den || !out) return HR_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return HR_EDEVICE;
+    const uint64_t blocks = (n + kBlock - 1) / kBlock;
+    if (blocks > 0xffffffffull) return HR_EINVAL;
+    k_quot_check<<<dim3((uint32_t)blocks), dim3(kBlock), 0, as_stream(stream)>>>(num, den, cap,
+                                                                                 out, n);
     return launched();
 }
 

@@ -141,3 +141,40 @@ def test_empty_input():
     e32 = torch.empty(0, dtype=torch.uint32, device="cuda")
     c, o, h, _ = api.search(e64, e64, e32, 1 << 40)
     assert c.numel() == 0 and h.numel() == 0
+
+
+def test_device_quotient_routine_exact():
+    """The partial-quotient routine (binary64 reciprocal estimate + exact
+    correction) against Python integer division, over every scale of
+    quotient, exact multiples, off-by-one neighbours and saturation."""
+    from paper_1211_3056_amd import _lib, api
+    g = synth.rng(77)
+    M = 1 << 64
+    nums, dens = [], []
+    for _ in range(200000):
+        den = int(g.integers(1, 2 ** 63)) >> int(g.integers(0, 63))
+        den = max(den, 1)
+        kind = int(g.integers(0, 4))
+        if kind == 0:
+            num = int(g.integers(0, 2 ** 63)) * 2 + int(g.integers(0, 2))
+        elif kind == 1:                       # exact multiple and neighbours
+            k = int(g.integers(0, 1 << 34))
+            num = min(k * den + int(g.integers(-1, 2)), M - 1)
+        elif kind == 2:                       # quotient near the cap
+            k = int(g.integers((1 << 32) - 8, (1 << 32) + 8))
+            num = min(k * den - int(g.integers(0, 2)), M - 1)
+        else:                                 # num near 2^64
+            num = M - 1 - int(g.integers(0, 1 << 20))
+        nums.append(max(num, 0) % M)
+        dens.append(den)
+    nums += [M - 1, M - 1, M - 2, 0, 1, (1 << 63) + 1]
+    dens += [1, M - 1, M - 1, 5, 1, (1 << 63) - 1]
+    num_t = api.to_dev(np.array(nums, np.uint64), torch.uint64)
+    den_t = api.to_dev(np.array(dens, np.uint64), torch.uint64)
+    for cap in (1, 65536, (1 << 32) - 1, 3000000000):
+        out = torch.empty(len(nums), dtype=torch.uint64, device="cuda")
+        _lib.hr_quot_check(api.context(), num_t, den_t, cap, out)
+        got = out.cpu().numpy()
+        want = np.array([min(n // d, cap) for n, d in zip(nums, dens)], np.uint64)
+        bad = np.nonzero(got != want)[0]
+        assert bad.size == 0, [(nums[i], dens[i], cap, int(got[i]), int(want[i])) for i in bad[:5]]

@@ -1,0 +1,122 @@
+"""CPU checks of the product's host preparation and planning (no GPU):
+tables equal the oracle's independently computed tables, every HR argument
+lies in the product's degree-1 window, the recheck thresholds never
+contradict per-argument brute force, and the autotuner's choices are sound."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import hr as ohr
+from oracle.search import brute_hits
+from oracle.tabulate import evaluate, piece_ab, straightforward_rows, top64
+from oracle.taylor import Job, initial_table
+from paper_1211_3056_amd import autotune
+from paper_1211_3056_amd.plan import BatchJob, plan_job
+from paper_1211_3056_amd.prep import JobSpec, SubPreparer, output_ulp_range, prepare
+
+STARTS = {"exp": 1.0, "exp2": 1.0, "log": 3.37, "sin": 1.0, "cos": 1.0}
+
+
+def _ints(table, W):
+    L = W // 64
+    return [sum(int(table[e, l]) << (64 * l) for l in range(L)) for e in range(table.shape[0])]
+
+
+def _rows_T(flat, d):
+    T, pos = [], 0
+    for j in range(d + 1):
+        T.append(flat[pos:pos + d - j + 1])
+        pos += d - j + 1
+    return T
+
+
+@pytest.mark.parametrize("fname", ["exp", "exp2", "log", "sin", "cos"])
+@pytest.mark.parametrize("W,delta,N,tau", [(128, 3, 1 << 6, 1 << 4), (256, 4, 1 << 9, 1 << 5)])
+def test_tables_equal_oracle(fname, W, delta, N, tau):
+    spec = JobSpec(fname, STARTS[fname], N * tau * 4, 20, "rn", N, tau, delta, W)
+    P = prepare(spec)
+    job = Job(fname, STARTS[fname], N * tau * 4, 20, "rn", N, tau, delta, W)
+    for r, t in enumerate(P.subs):
+        flat = [v for row in initial_table(job, int(t)) for v in row]
+        assert _ints(P.tables[r], W) == flat
+
+
+@pytest.mark.parametrize("fname", ["exp", "exp2", "log", "sin", "cos"])
+@pytest.mark.parametrize("mode", ["rn", "dir"])
+def test_windows_and_thresholds_against_bruteforce(fname, mode):
+    """Every HR argument of each piece is a candidate of the product's
+    window; every value the thresholds call certain agrees with brute force."""
+    N, tau, d, W = 1 << 6, 1 << 4, 3, 128
+    spec = JobSpec(fname, STARTS[fname], N * tau * 8, 8, mode, N, tau, d, W)
+    job = Job(fname, STARTS[fname], N * tau * 8, 8, mode, N, tau, d, W)
+    cases = set(ohr.hr_bruteforce(job))
+    assert len(cases) > 20
+    P = prepare(spec)
+    n_cand = 0
+    for r, t in enumerate(P.subs):
+        T = _rows_T(_ints(P.tables[r], W), d)
+        lo, width = int(P.win[r, 0]), int(P.win[r, 1])
+        hr_lo, hr_hi, rej_lo, rej_hi = (int(x) for x in P.thr[r])
+        for i in range(tau):
+            rows = straightforward_rows(T, d, i, W)
+            a, b = piece_ab(rows, W)
+            cand = set(brute_hits(a, b, N, width, lo=lo))
+            n_cand += len(cand)
+            base = int(t) * spec.per_sub + i * N
+            for x in range(N):
+                m = base + x
+                tv = top64(evaluate(rows, x, W), W)
+                if m in cases:
+                    assert x in cand
+                    assert not (rej_lo <= tv <= rej_hi)
+                elif hr_lo <= tv <= hr_hi:
+                    pytest.fail(f"value certain HR but brute force says no: {m}")
+    assert n_cand < spec.count          # the window actually filters
+
+
+def test_partial_subintervals_prepare_like_whole_ones():
+    """A sub-interval cut short keeps the table of its start; only the error
+    budget (length, tau) changes."""
+    uf = output_ulp_range("exp", 1.0, 1 << 20)
+    sp = SubPreparer("exp", 1.0, 20, "rn", 3, 128, uf)
+    t_full, w_full, _ = sp.prepare(1 << 16, 1 << 16, 1000)
+    t_part, w_part, _ = sp.prepare(1 << 16, 12345, 1000)
+    assert np.array_equal(t_full, t_part)
+    assert int(w_part[1]) <= int(w_full[1])
+
+
+def test_autotuner_choices():
+    uf = output_ulp_range("exp", 1.0, 1 << 40)
+    # degree: the 2^28-argument sub-intervals of the batch workload need 3
+    assert autotune.choose_degree("exp", 1.0, 1 << 28, 28, uf) == 3
+    assert autotune.choose_degree("exp", 1.0, 1 << 20, 28, uf) <= 2
+    # width grows with the table-rounding amplification
+    assert autotune.choose_width([(1 << 12, 1 << 16)], 3, 28) == 128
+    assert autotune.choose_width([(1 << 20, 1 << 16)], 4, 32) >= 192
+    # piece length: tighter thresholds favour shorter pieces
+    assert autotune.choose_N("exp", 1.0, 1 << 36, 28, uf) <= autotune.choose_N("exp", 1.0, 1 << 36, 20, uf)
+    # item split covers every piece exactly once, 64 lanes x nu each
+    items = autotune.split_sub(1000, 1 << 12, 5000.0, 50.0)
+    assert sum(n for _, n, _ in items) == 1000
+    assert all(n <= 64 * nu for _, n, nu in items)
+    assert [p for p, _, _ in items] == sorted(p for p, _, _ in items)
+
+
+def test_plan_job_ragged_ranges():
+    pj = plan_job(BatchJob("sin", 1.25, 300_001, 11, "rn", sub_len=65_536, N=[1000, 777, 4096, 333, 5000]))
+    assert [s.length for s in pj.subs] == [65536] * 4 + [300_001 - 4 * 65536]
+    assert sum(s.length for s in pj.subs) == 300_001
+    assert pj.subs[-1].pieces == math.ceil(pj.subs[-1].length / 5000)
+    with pytest.raises(ValueError):
+        plan_job(BatchJob("exp", 1.3862943, 1 << 40, 20, "rn"))      # crosses 4
+
+
+def test_workload_generators_are_seeded():
+    a, b = synth.config4(), synth.config4()
+    assert a == b and len(a) == 16
+    c5 = synth.config5(n_jobs=50)
+    assert c5 == synth.config5(n_jobs=50)
+    for d in c5:
+        output_ulp_range(d["fname"], d["X0"], d["count"])     # one output binade each
