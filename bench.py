@@ -39,6 +39,9 @@ def parse():
     p.add_argument("--no-serve", action="store_true", help="skip the serving workload")
     p.add_argument("--serve-jobs", type=int, default=2000)
     p.add_argument("--prep-workers", type=int, default=16)
+    p.add_argument("--probe", action="store_true",
+                   help="profiling probe: a 1 GiB device copy, then 3 fused passes of the "
+                        "2^40 slice and 3 batched passes of the 16-job mix; no JSON")
     return p.parse_args()
 
 
@@ -75,6 +78,9 @@ def main():
     from paper_1211_3056_amd.prep import JobSpec, prepare
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.probe:
+        probe()
+        return
     spec = JobSpec(**synth.CONFIG3)
     t0 = time.time()
     P = prepare(spec)
@@ -86,7 +92,7 @@ def main():
     cap = 1 << 16
     out = torch.empty(cap * _lib.RESULT_BYTES, dtype=torch.uint8, device=dev)
     count = torch.zeros(1, dtype=torch.uint64, device=dev)
-    stats = torch.zeros(4, dtype=torch.uint64, device=dev)
+    stats = torch.zeros(8, dtype=torch.uint64, device=dev)
     count_h = torch.zeros(1, dtype=torch.uint64).pin_memory()
     res_h = torch.zeros(cap * _lib.RESULT_BYTES, dtype=torch.uint8).pin_memory()
     n_sub = spec.n_sub
@@ -148,7 +154,9 @@ def main():
                      "frac": achieved / (PEAK_INT32_OPS / 1e12), "traffic": None,
                      "kernel": "k_pipeline<8,4>", "kernel_ms": kern_avg},
         "hr_cases": hr_cases, "undecided": undecided, "candidates": cand,
-        "partial_quotients": quot, "host_prep_s": prep_s,
+        "partial_quotients": quot, "quotients_per_piece": quot / max(pieces, 1),
+        "nmdm_wave64": 1.0 - quot / int(st[4]) if int(st[4]) else 0.0,
+        "host_prep_s": prep_s,
         "end_to_end_args_per_s": args_total / (prep_s + ms_per_step / 1000),
     }
     if not args.no_plain:
@@ -182,6 +190,32 @@ def main():
     print(json.dumps(line))
 
 
+def probe():
+    """Kernels for counter runs: a plain copy of known size (the reference
+    for scaling FETCH_SIZE / WRITE_SIZE), the fused pass, the batched pass."""
+    import torch
+
+    import synth
+    from paper_1211_3056_amd import api, batch, pipeline
+    from paper_1211_3056_amd.prep import JobSpec, prepare
+
+    src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    spec = JobSpec(**synth.CONFIG3)
+    P = prepare(spec)
+    dev = pipeline.upload(P)
+    for _ in range(3):
+        pipeline.run_fused(P, dev)
+    dp = batch.DevicePlan(batch.build_plan([batch.BatchJob(**d) for d in synth.config4()]))
+    run = batch.Runner(dp)
+    for _ in range(3):
+        run.batched()
+    torch.cuda.synchronize()
+    print("probe done", file=sys.stderr)
+
+
 def bench_batch(args):
     """16 jobs (exp, log, 2^x, sin; 2^30..2^38 arguments each; N uniform in
     [2^12, 2^20] per sub-interval; eps = 2^-28): one persistent launch vs one
@@ -205,6 +239,17 @@ def bench_batch(args):
         res_b = run.batched()
         tb.append(time.perf_counter() - t0)
     st = run.stats_dict()
+    graph = run.capture()
+    graph.replay()
+    graph.results()
+    tg = []
+    for _ in range(max(3, args.steps // 2)):
+        t0 = time.perf_counter()
+        graph.replay()
+        res_g = graph.results()
+        tg.append(time.perf_counter() - t0)
+    same_graph = np.array_equal(np.sort(res_g, order=["job", "sub", "piece", "k"]),
+                                np.sort(res_b, order=["job", "sub", "piece", "k"]))
     run.plain()
     tp = []
     for _ in range(2):
@@ -224,7 +269,10 @@ def bench_batch(args):
             "batched_ms": b_s * 1000, "plain_ms": p_s * 1000,
             "batched_args_per_s": n_args / b_s, "plain_args_per_s": n_args / p_s,
             "speedup": p_s / b_s, "identical_results": bool(same),
+            "graph_ms": min(tg) * 1000, "graph_speedup": p_s / min(tg),
+            "graph_identical": bool(same_graph),
             "hr_cases": sum(len(v) for v in hr.values()), "candidates": st["candidates"],
+            "nmdm_wave64": st["nmdm"],
             "host_prep_s": plan.prep_s}
 
 

@@ -183,8 +183,12 @@ typedef struct {
  * (b - lo - k a) mod 2^64 < d, as in hr_search.  Each candidate is evaluated
  * exactly and classified; results of class 1 and 2 are appended to `out`
  * (capacity cap entries, order unspecified); *count (device) receives their
- * number (may exceed cap).  stats (device, uint64[4], may be NULL) is
- * incremented by: pieces, candidates, results, partial quotients.
+ * number (may exceed cap).  stats (device, uint64[8], may be NULL) is
+ * incremented by: [0] pieces, [1] candidates, [2] results, [3] partial
+ * quotients, [4] wave slots spent in the closest-point walk (sum over waves
+ * and pieces of the slowest lane's partial quotients times the live lanes;
+ * 1 - [3]/[4] is the loop divergence NMDM of the paper's Sec. 2.2);
+ * [5..7] reserved.
  * Errors: as hr_tabulate / hr_recheck, N == 0, or N^degree >= 2^128.
  */
 hr_status hr_pipeline(hr_ctx* ctx, const uint64_t* table, uint32_t n_sub, uint32_t degree,

@@ -144,8 +144,14 @@ def hr_recheck(ctx, table, n_sub, degree, tau, width, cand_inst, cand_k, max_k, 
                                           _p(thr), _p(value_out), _p(class_out), _stream(stream)))
 
 
+def _stats_ok(stats):
+    if stats is not None and stats.numel() < 8:
+        raise ValueError("stats needs 8 uint64 entries")
+
+
 def hr_pipeline(ctx, table, n_sub, degree, tau, width, N, win, thr, out, cap, count, stats,
                 stream=None):
+    _stats_ok(stats)
     _check("hr_pipeline", lib().hr_pipeline(ctx.handle, _p(table), n_sub, degree, tau, width, N,
                                             _p(win), _p(thr), _p(out), cap, _p(count), _p(stats),
                                             _stream(stream)))
@@ -153,6 +159,7 @@ def hr_pipeline(ctx, table, n_sub, degree, tau, width, N, win, thr, out, cap, co
 
 def hr_batch_run(ctx, pool, items, n_items, width, degree, waves, out, cap, count, stats,
                  stream=None):
+    _stats_ok(stats)
     _check("hr_batch_run", lib().hr_batch_run(ctx.handle, _p(pool), _p(items), n_items, width,
                                               degree, waves, _p(out), cap, _p(count), _p(stats),
                                               _stream(stream)))

@@ -99,7 +99,7 @@ def pipeline(table, n_sub, degree, tau, width, N, win, thr, cap=1 << 16, ctx=Non
     while True:
         out = torch.empty(max(cap, 1) * _lib.RESULT_BYTES, dtype=torch.uint8, device=dev)
         count = torch.zeros(1, dtype=torch.uint64, device=dev)
-        stats = torch.zeros(4, dtype=torch.uint64, device=dev)
+        stats = torch.zeros(8, dtype=torch.uint64, device=dev)
         _lib.hr_pipeline(ctx, table, n_sub, degree, tau, width, N, win, thr, out, cap, count,
                          stats, stream)
         torch.cuda.synchronize(dev)

@@ -125,7 +125,7 @@ class Runner:
         dev = dp.pool.device
         self.out = torch.empty(cap * _lib.RESULT_BYTES, dtype=torch.uint8, device=dev)
         self.count = torch.zeros(1, dtype=torch.uint64, device=dev)
-        self.stats = torch.zeros(4, dtype=torch.uint64, device=dev)
+        self.stats = torch.zeros(8, dtype=torch.uint64, device=dev)
 
     def _results(self):
         n = api._u64_scalar(self.count)
@@ -177,10 +177,59 @@ class Runner:
             parts.append(self._results())
         return np.concatenate(parts) if parts else np.zeros(0, api.RESULT_DTYPE)
 
+    def capture(self, waves: int | None = None, cap: int | None = None):
+        """Capture the batched launch sequence (counter fills + one persistent
+        launch per group) in a HIP graph; returns a GraphRun with its own
+        fixed-size output buffers (results beyond `cap` raise on read).
+        Counters are cleared by fill kernels inside the graph, never by
+        memset nodes."""
+        waves = waves or device_waves()
+        cap = cap or self.cap
+        dev = self.dp.pool.device
+        out = torch.empty(cap * _lib.RESULT_BYTES, dtype=torch.uint8, device=dev)
+        count = torch.zeros(1, dtype=torch.uint64, device=dev)
+        stats = torch.zeros(8, dtype=torch.uint64, device=dev)
+
+        def launches(stream):
+            count.zero_()
+            stats.zero_()
+            for W, d, first, n in self.dp.groups:
+                _run(self.ctx, self.dp, self.dp.sorted_items, first, n, W, d, waves, out, cap,
+                     count, stats, stream)
+
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):        # warm up: context scratch exists
+            launches(None)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            launches(None)
+        return GraphRun(g, out, count, stats, cap)
+
     def stats_dict(self):
         st = self.stats.cpu().numpy()
         return {"pieces": int(st[0]), "candidates": int(st[1]), "results": int(st[2]),
-                "partial_quotients": int(st[3])}
+                "partial_quotients": int(st[3]),
+                "nmdm": 1.0 - int(st[3]) / int(st[4]) if int(st[4]) else 0.0}
+
+
+class GraphRun:
+    """A captured batched pass: replay() relaunches it, results() reads it."""
+
+    def __init__(self, graph, out, count, stats, cap):
+        self.graph, self.out, self.count, self.stats, self.cap = graph, out, count, stats, cap
+
+    def replay(self):
+        self.graph.replay()
+
+    def results(self):
+        torch.cuda.synchronize()
+        n = api._u64_scalar(self.count)
+        if n > self.cap:
+            raise _lib.HRError("hr_batch_run", _lib.HR_ECAPACITY)
+        return self.out[: n * _lib.RESULT_BYTES].cpu().numpy().view(api.RESULT_DTYPE).copy()
 
 
 def finish(plan: Plan, results: np.ndarray):

@@ -296,11 +296,11 @@ HR_HD void wzero(Word<L>& a) {
     for (int i = 0; i < L; ++i) a.w[i] = 0;
 }
 
-// acc += x * m mod 2^(32 L), m a 128-bit multiplier given as 4 limbs.
-template <int L>
-HR_HD void wmac128(Word<L>& acc, const Word<L>& x, const uint32_t m[4]) {
+// acc += x * m mod 2^(32 L), m a multiplier of M 32-bit limbs.
+template <int L, int M>
+HR_HD void wmac_n(Word<L>& acc, const Word<L>& x, const uint32_t* m) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < M; ++j) {
         if (j >= L) break;
         const uint32_t mj = m[j];
         uint32_t carry = 0;
@@ -310,6 +310,20 @@ HR_HD void wmac128(Word<L>& acc, const Word<L>& x, const uint32_t m[4]) {
             acc.w[i + j] = (uint32_t)t;
             carry = (uint32_t)(t >> 32);
         }
+    }
+}
+
+// acc += x * m mod 2^(32 L), m a 128-bit multiplier given as 4 limbs; the
+// high limbs are skipped when they are zero (small binomials).
+template <int L>
+HR_HD void wmac128(Word<L>& acc, const Word<L>& x, const uint32_t m[4]) {
+    if ((m[2] | m[3]) == 0) {
+        if (m[1] == 0) wmac_n<L, 1>(acc, x, m);
+        else wmac_n<L, 2>(acc, x, m);
+    } else if (m[3] == 0) {
+        wmac_n<L, 3>(acc, x, m);
+    } else {
+        wmac_n<L, 4>(acc, x, m);
     }
 }
 

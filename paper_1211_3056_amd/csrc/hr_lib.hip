@@ -44,6 +44,15 @@ __device__ uint64_t wave_incl_scan(uint64_t v) {
     return v;
 }
 
+__device__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t t = __shfl_xor(v, o, 64);
+        v = t > v ? t : v;
+    }
+    return v;
+}
+
 __device__ uint64_t wave_sum(uint64_t v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -311,18 +320,14 @@ __device__ __forceinline__ void fused_wave(
     uint32_t last_piece, uint32_t last_N, uint64_t wlo, uint64_t wd, uint32_t* s_rows,
     uint32_t* s_qlane, uint32_t* s_qk, OriginFn&& origin, hr_result* __restrict__ out,
     uint64_t cap, unsigned long long* __restrict__ count, uint64_t& n_pieces, uint64_t& n_cand,
-    uint64_t& n_res, uint64_t& n_steps) {
+    uint64_t& n_res, uint64_t& n_steps, uint64_t& n_slots) {
     const int lane = threadIdx.x;
     for (uint32_t s = 0; s < nu; ++s) {
         const bool live = active && s < cnt;
-#pragma unroll
-        for (int j = 0; j <= DEG; ++j)
-#pragma unroll
-            for (int w = 0; w < L; ++w) s_rows[(j * L + w) * 64 + lane] = v[entry(DEG, j, 0)].w[w];
         hr::HitIter it;
         it.done = true;
+        uint32_t steps = 0;
         if (live) {
-            uint32_t steps = 0;
             const uint64_t piece = p_begin + s;
             const uint32_t n = (piece == last_piece) ? last_N : N;
             const uint64_t bb = top64(v[entry(DEG, 0, 0)]) - wlo;
@@ -330,6 +335,18 @@ __device__ __forceinline__ void fused_wave(
             hr::iter_init(it, aa, bb, n, wd, &steps);
             ++n_pieces;
             n_steps += steps;
+        }
+        {   // loop divergence: the wave runs as long as its slowest lane
+            const uint32_t wmax = wave_max_u32(steps);
+            const uint32_t nlive = (uint32_t)__popcll(__ballot(live));
+            if (lane == 0) n_slots += (uint64_t)wmax * nlive;
+        }
+        if (!it.done) {   // only pieces with candidates publish their rows
+#pragma unroll
+            for (int j = 0; j <= DEG; ++j)
+#pragma unroll
+                for (int w = 0; w < L; ++w)
+                    s_rows[(j * L + w) * 64 + lane] = v[entry(DEG, j, 0)].w[w];
         }
         for (;;) {
             uint32_t qn = 0;
@@ -392,12 +409,14 @@ __device__ __forceinline__ void fused_wave(
 }
 
 __device__ __forceinline__ void flush_stats(unsigned long long* stats, uint64_t n_pieces,
-                                            uint64_t n_cand, uint64_t n_res, uint64_t n_steps) {
+                                            uint64_t n_cand, uint64_t n_res, uint64_t n_steps,
+                                            uint64_t n_slots) {
     if (!stats) return;
     n_pieces = wave_sum(n_pieces);
     n_cand = wave_sum(n_cand);
     n_res = wave_sum(n_res);
     n_steps = wave_sum(n_steps);
+    n_slots = wave_sum(n_slots);
     if (threadIdx.x == 0) {
         atomicAdd(stats + 0, (unsigned long long)n_pieces);
         atomicAdd(stats + 1, (unsigned long long)n_cand);
@@ -442,7 +461,7 @@ __global__ __launch_bounds__(64) void k_pipeline(
     }
     const uint64_t wlo = active ? win[2 * sub] : 0;
     const uint64_t wd = active ? win[2 * sub + 1] : 0;
-    uint64_t n_pieces = 0, n_cand = 0, n_res = 0, n_steps = 0;
+    uint64_t n_pieces = 0, n_cand = 0, n_res = 0, n_steps = 0, n_slots = 0;
     auto origin = [&](uint32_t src, uint32_t s) {
         const uint64_t g = (uint64_t)blockIdx.x * 64 + src;
         const uint64_t ssub = g / per_sub;
@@ -454,8 +473,8 @@ __global__ __launch_bounds__(64) void k_pipeline(
         return o;
     };
     fused_wave<L, DEG>(v, active, cnt, nu, i0, N, 0xffffffffu, 0, wlo, wd, s_rows, s_qlane, s_qk,
-                       origin, out, cap, count, n_pieces, n_cand, n_res, n_steps);
-    flush_stats(stats, n_pieces, n_cand, n_res, n_steps);
+                       origin, out, cap, count, n_pieces, n_cand, n_res, n_steps, n_slots);
+    flush_stats(stats, n_pieces, n_cand, n_res, n_steps, n_slots);
 }
 
 // Work items of uneven size (hr_batch_run).  PERSIST: a fixed grid of waves
@@ -471,7 +490,7 @@ __global__ __launch_bounds__(64) void k_items(
     __shared__ uint32_t s_qlane[kQueue];
     __shared__ uint32_t s_qk[kQueue];
     const int lane = threadIdx.x;
-    uint64_t n_pieces = 0, n_cand = 0, n_res = 0, n_steps = 0;
+    uint64_t n_pieces = 0, n_cand = 0, n_res = 0, n_steps = 0, n_slots = 0;
     uint32_t idx;
     if (PERSIST) {
         uint32_t c = 0;
@@ -509,7 +528,7 @@ __global__ __launch_bounds__(64) void k_items(
         };
         fused_wave<L, DEG>(v, active, cnt, nu, p_begin, I->N, I->last_piece, I->last_N, I->win_lo,
                            I->win_d, s_rows, s_qlane, s_qk, origin, out, cap, count, n_pieces,
-                           n_cand, n_res, n_steps);
+                           n_cand, n_res, n_steps, n_slots);
         if (PERSIST) {
             uint32_t c = 0;
             if (lane == 0) c = atomicAdd(next, 1u);
@@ -518,7 +537,7 @@ __global__ __launch_bounds__(64) void k_items(
             idx = n_items;
         }
     }
-    flush_stats(stats, n_pieces, n_cand, n_res, n_steps);
+    flush_stats(stats, n_pieces, n_cand, n_res, n_steps, n_slots);
 }
 
 __global__ void k_zero_u32(unsigned int* p) { *p = 0u; }

@@ -126,7 +126,7 @@ class GpuBackend:
         self.waves = waves or device_waves()
         self.out = torch.empty(cap * _lib.RESULT_BYTES, dtype=torch.uint8, device="cuda")
         self.count = torch.zeros(1, dtype=torch.uint64, device="cuda")
-        self.stats = torch.zeros(4, dtype=torch.uint64, device="cuda")
+        self.stats = torch.zeros(8, dtype=torch.uint64, device="cuda")
         self.steps = 0
 
     def free_memory(self) -> int:
@@ -199,10 +199,13 @@ class Server:
         self.peak_used = 0
         self.blocked_admissions = 0
 
-    def serve(self, jobs, arrivals, realtime: bool = True):
+    def serve(self, jobs, arrivals, realtime: bool = True, prepared=None):
         """Run every job; arrivals[i] is job i's arrival time in seconds from
-        the start.  Returns the list of JobState in job order."""
+        the start.  `prepared` (optional) maps job_id to a Prepared made
+        ahead of time (cached tables): such jobs skip the worker pool.
+        Returns the list of JobState in job order."""
         states = [JobState(j, float(a)) for j, a in zip(jobs, arrivals)]
+        prepared = prepared or {}
         order = sorted(range(len(states)), key=lambda i: states[i].arrival)
         t0 = self.clock()
         now = lambda: self.clock() - t0
@@ -216,9 +219,14 @@ class Server:
             # arrivals -> preparation
             while nxt < len(order) and (not realtime or states[order[nxt]].arrival <= t):
                 st = states[order[nxt]]
+                nxt += 1
+                if st.job.job_id in prepared:
+                    st.prep = prepared[st.job.job_id]
+                    st.status, st.t_ready = "ready", now()
+                    ready.append(st)
+                    continue
                 st.status = "preparing"
                 futures[self.pool.submit(prepare_job, st.job)] = st
-                nxt += 1
             # finished preparations -> ready queue (arrival order kept by FIFO of completion)
             for fut in [f for f in futures if f.done()]:
                 st = futures.pop(fut)

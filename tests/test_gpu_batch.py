@@ -107,3 +107,21 @@ def test_mixed_widths_degrees_and_ragged_ranges():
     hr = batch.finish(plan, b)
     for pj in plan.jobs:
         assert hr[pj.job.job_id] == oracle_job(pj), pj.job.fname
+
+
+def test_graph_replays_match_eager():
+    """The captured batched pass, replayed several times with eager work in
+    between, gives the eager result every time."""
+    from paper_1211_3056_amd import batch
+    jobs = _scaled_jobs(scale_log2=16, N_scale_log2=8, s=13)
+    dp = batch.DevicePlan(batch.build_plan(jobs, target_items=2048))
+    run = batch.Runner(dp)
+    eager = _sorted(run.batched())
+    graph = run.capture()
+    for rep in range(4):
+        graph.replay()
+        got = _sorted(graph.results())
+        assert got.tobytes() == eager.tobytes(), rep
+        # eager work between replays: a plain pass and a torch reduction
+        assert _sorted(run.plain()).tobytes() == eager.tobytes()
+        torch.arange(1 << 20, device="cuda").sum().item()

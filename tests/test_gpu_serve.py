@@ -63,9 +63,10 @@ def test_small_budget_admission_on_device(pool):
     from paper_1211_3056_amd import serve
     be = serve.GpuBackend()
     jobs = _jobs(12)
-    fp = max(serve.prepare_job(j).footprint for j in jobs)
+    preps = {j.job_id: serve.prepare_job(j) for j in jobs}
+    fp = max(p.footprint for p in preps.values())
     srv = serve.Server(be, pool, hbm_budget=2 * fp)
-    states = srv.serve(jobs, np.zeros(len(jobs)), realtime=False)
+    states = srv.serve(jobs, np.zeros(len(jobs)), realtime=False, prepared=preps)
     assert all(s.status == "done" for s in states)
     assert srv.blocked_admissions > 0 and srv.peak_used <= 2 * fp
     ref = serve.Server(be, pool).serve(jobs, np.zeros(len(jobs)), realtime=False)

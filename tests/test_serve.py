@@ -10,8 +10,9 @@ from paper_1211_3056_amd.plan import RESULT_DTYPE, BatchJob
 class FakeBackend:
     """Runs nothing; records which jobs each step carried."""
 
-    def __init__(self, free=1 << 30, fail_on=None):
+    def __init__(self, free=1 << 30, fail_on=None, delay=0.0):
         self.free = free
+        self.delay = delay
         self.steps = []
         self.fail_on = fail_on
         self.resident = set()
@@ -28,6 +29,8 @@ class FakeBackend:
         self.resident.discard(st.job.job_id)
 
     def step(self, states):
+        import time
+        time.sleep(self.delay)
         ids = [s.job.job_id for s in states]
         self.steps.append(ids)
         if self.fail_on is not None and self.fail_on in ids:
@@ -58,7 +61,7 @@ def test_all_jobs_complete_in_arrival_order(pool):
 
 
 def test_small_budget_blocks_admission(pool):
-    be = FakeBackend()
+    be = FakeBackend(delay=0.05)      # device steps outlast preparations
     jobs = _jobs(6)
     fp = serve.prepare_job(jobs[0]).footprint
     srv = serve.Server(be, pool, hbm_budget=int(fp * 1.5))
@@ -106,3 +109,14 @@ def test_summary_fields(pool):
     states = serve.Server(be, pool, hbm_budget=1 << 30).serve(_jobs(3), np.zeros(3))
     s = serve.summarize(states)
     assert s["done"] == 3 and s["jobs_per_s"] > 0 and s["p99_latency_ms"] >= s["p50_latency_ms"]
+
+
+def test_prepared_jobs_skip_the_pool(pool):
+    be = FakeBackend()
+    jobs = _jobs(5)
+    preps = {j.job_id: serve.prepare_job(j) for j in jobs}
+    fp = max(p.footprint for p in preps.values())
+    srv = serve.Server(be, pool, hbm_budget=int(fp * 1.5))
+    states = srv.serve(jobs, np.zeros(5), realtime=False, prepared=preps)
+    assert all(s.status == "done" for s in states)
+    assert srv.blocked_admissions >= 4 and be.max_resident == 1
