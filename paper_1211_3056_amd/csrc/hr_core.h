@@ -45,14 +45,18 @@ HR_HD double fdiv_est(double num, double den) {
 HR_HD uint64_t quot_sat(uint64_t num, uint64_t den, uint64_t cap) {
     const double e = fdiv_est((double)num, (double)den);
     if (e > (double)cap + 2.0) return cap;
-    uint64_t k = (uint64_t)(uint32_t)__builtin_fmin(e, 4294967295.0);
-    const uint64_t lo = k * den;
-    if (mulhi64(k, den) != 0 || lo > num) {
-        k -= 1;
+    uint32_t k = (uint32_t)__builtin_fmin(e, 4294967295.0);
+    // k * den as a 96-bit product: lo (64 bits) and whether bits >= 64 are set
+    const uint64_t t1 = (uint64_t)k * (uint32_t)den;
+    const uint64_t t2 = (uint64_t)k * (uint32_t)(den >> 32) + (t1 >> 32);
+    const uint64_t lo = (t2 << 32) | (uint32_t)t1;
+    uint64_t kk = k;
+    if ((t2 >> 32) != 0 || lo > num) {
+        kk -= 1;
     } else if (num - lo >= den) {
-        k += 1;
+        kk += 1;
     }
-    return k < cap ? k : cap;
+    return kk < cap ? kk : cap;
 }
 
 // floor(a / b) for 0 <= a < 2^53, 0 < b < 2^53 (indices): the correctly
@@ -120,7 +124,9 @@ HR_HD void closest_left(uint64_t a, uint64_t b, uint64_t n, Near& r) {
             if (p < q) {
                 k = quot_sat(q, p, n);
                 if (X >= iq) {   // b inside a q-interval: it is split at p, 2p, ..
-                    const uint64_t s = umin(umin(quot_sat(d, p, n), k), idx_div(n - 1 - X, ip));
+                    uint64_t s = umin(quot_sat(d, p, n), k);
+                    // only points with index < n exist (matters in the last step)
+                    if (X + s * ip > n - 1) s = idx_div(n - 1 - X, ip);
                     X += s * ip;
                     d -= s * p;
                 }

@@ -495,7 +495,7 @@ __global__ __launch_bounds__(64) void k_items(
     if (PERSIST) {
         uint32_t c = 0;
         if (lane == 0) c = atomicAdd(next, 1u);
-        idx = __shfl(c, 0, 64);
+        idx = __builtin_amdgcn_readfirstlane(c);   // wave-uniform item index
     } else {
         idx = blockIdx.x;
     }
@@ -532,7 +532,7 @@ __global__ __launch_bounds__(64) void k_items(
         if (PERSIST) {
             uint32_t c = 0;
             if (lane == 0) c = atomicAdd(next, 1u);
-            idx = __shfl(c, 0, 64);
+            idx = __builtin_amdgcn_readfirstlane(c);   // wave-uniform item index
         } else {
             idx = n_items;
         }

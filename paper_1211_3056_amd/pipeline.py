@@ -50,8 +50,12 @@ def run_plain(P: Prepared, dev_args=None, ctx=None):
     N = api.to_dev(np.full(n_sub * spec.tau, spec.N, np.uint32), torch.uint32, a.device)
     lo = api.to_dev(P.win[:, 0], torch.uint64, a.device)
     d = api.to_dev(P.win[:, 1], torch.uint64, a.device)
+    # expected candidates: every argument of a sub-interval lands in its
+    # window with probability d / 2^64; size the buffer for one pass
+    expect = float(P.win[:, 1].astype(np.float64).sum()) / 2.0 ** 64 * spec.per_sub
+    cap = int(expect * 1.25) + (1 << 16)
     counts, offsets, hits, inst = api.search(a, b, N, d, lo=lo, group=spec.tau, with_inst=True,
-                                             ctx=ctx)
+                                             cap=cap, ctx=ctx)
     value, cls = api.recheck(table, n_sub, spec.delta, spec.tau, spec.W, inst, hits, spec.N - 1,
                              thr, ctx=ctx)
     cls_h = cls.cpu().numpy()
