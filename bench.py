@@ -66,6 +66,8 @@ def main():
               "box in this setup has a single MI355X", file=sys.stderr)
         sys.exit(2)
     pool = None
+    if args.probe:
+        args.no_serve = True
     if not args.no_serve:
         # preparation workers come from a forkserver started before the GPU is used
         from paper_1211_3056_amd import serve

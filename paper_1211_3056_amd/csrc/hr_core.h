@@ -44,19 +44,16 @@ HR_HD double fdiv_est(double num, double den) {
 // quotients saturate at cap: callers only need to know that they reach cap.
 HR_HD uint64_t quot_sat(uint64_t num, uint64_t den, uint64_t cap) {
     const double e = fdiv_est((double)num, (double)den);
-    if (e > (double)cap + 2.0) return cap;
+    const bool big = e > (double)cap + 2.0;
     uint32_t k = (uint32_t)__builtin_fmin(e, 4294967295.0);
     // k * den as a 96-bit product: lo (64 bits) and whether bits >= 64 are set
     const uint64_t t1 = (uint64_t)k * (uint32_t)den;
     const uint64_t t2 = (uint64_t)k * (uint32_t)(den >> 32) + (t1 >> 32);
     const uint64_t lo = (t2 << 32) | (uint32_t)t1;
-    uint64_t kk = k;
-    if ((t2 >> 32) != 0 || lo > num) {
-        kk -= 1;
-    } else if (num - lo >= den) {
-        kk += 1;
-    }
-    return kk < cap ? kk : cap;
+    const bool over = (t2 >> 32) != 0 || lo > num;
+    const bool under = !over && num - lo >= den;
+    const uint64_t kk = (uint64_t)k - over + under;
+    return (big || kk >= cap) ? cap : kk;
 }
 
 // floor(a / b) for 0 <= a < 2^53, 0 < b < 2^53 (indices): the correctly
@@ -117,50 +114,54 @@ HR_HD void closest_left(uint64_t a, uint64_t b, uint64_t n, Near& r) {
         v = umin(k, n - 1);
         beta = 0 - v * a;
     } else {
-        q = 0 - k * a;   // 2^64 mod a
+        q = 0 - k * a;   // 2^64 mod a < a: the lengths now alternate, p > q first
         iq = k;
+        // Each pass reduces p by q, then q by p (two partial quotients, as in
+        // the paper's unrolled Alg. 4: which length shrinks alternates, so no
+        // test on it is needed).  Where b sits is a select, not a branch.
         for (;;) {
+            // ---- p > q: p-intervals (left ends < iq) get points at p - q, p - 2q, ..
             ++steps;
-            if (p < q) {
-                k = quot_sat(q, p, n);
-                if (X >= iq) {   // b inside a q-interval: it is split at p, 2p, ..
-                    uint64_t s = umin(quot_sat(d, p, n), k);
-                    // only points with index < n exist (matters in the last step)
-                    if (X + s * ip > n - 1) s = idx_div(n - 1 - X, ip);
-                    X += s * ip;
-                    d -= s * p;
-                }
-                if (ip + iq + k * ip >= n) {
-                    const uint64_t sv = umin(k, idx_div(n - 1 - iq, ip));
-                    u = ip;
-                    alpha = p;
-                    v = iq + sv * ip;
-                    beta = q - sv * p;
-                    break;
-                }
-                q -= k * p;
-                iq += k * ip;
-            } else {
-                k = quot_sat(p, q, n);
-                if (X < iq) {    // b inside a p-interval: points at p - q, p - 2q, ..
-                    // the first of them at or left of b: s = ceil((p - d) / q)
-                    const uint64_t s = quot_sat(p - d - 1, q, n) + 1;
-                    if (s <= k && X + ip + s * iq < n) {
-                        X += ip + s * iq;
-                        d -= p - s * q;
-                    }
-                }
-                if (ip + iq + k * iq >= n) {
-                    const uint64_t su = umin(k, idx_div(n - 1 - ip, iq));
-                    v = iq;
-                    beta = q;
-                    u = ip + su * iq;
-                    alpha = p - su * q;
-                    break;
-                }
-                p -= k * q;
-                ip += k * iq;
+            k = quot_sat(p, q, n);
+            {
+                const bool in_p = X < iq;
+                // the first new point at or left of b: s = ceil((p - d) / q)
+                const uint64_t s = quot_sat(in_p ? p - d - 1 : 0, q, n) + 1;
+                const bool take = in_p && s <= k && X + ip + s * iq < n;
+                X = take ? X + ip + s * iq : X;
+                d = take ? d - (p - s * q) : d;
             }
+            if (ip + iq + k * iq >= n) {
+                const uint64_t su = umin(k, idx_div(n - 1 - ip, iq));
+                v = iq;
+                beta = q;
+                u = ip + su * iq;
+                alpha = p - su * q;
+                break;
+            }
+            p -= k * q;
+            ip += k * iq;
+            // ---- q > p: q-intervals (left ends >= iq) get points at p, 2p, ..
+            ++steps;
+            k = quot_sat(q, p, n);
+            {
+                const bool in_q = X >= iq;
+                uint64_t s = in_q ? umin(quot_sat(d, p, n), k) : 0;
+                // only points with index < n exist (matters in the last step)
+                if (X + s * ip > n - 1) s = idx_div(n - 1 - X, ip);
+                X += s * ip;
+                d -= s * p;
+            }
+            if (ip + iq + k * ip >= n) {
+                const uint64_t sv = umin(k, idx_div(n - 1 - iq, ip));
+                u = ip;
+                alpha = p;
+                v = iq + sv * ip;
+                beta = q - sv * p;
+                break;
+            }
+            q -= k * p;
+            iq += k * ip;
         }
     }
     r.x = X;

@@ -422,6 +422,7 @@ __device__ __forceinline__ void flush_stats(unsigned long long* stats, uint64_t 
         atomicAdd(stats + 1, (unsigned long long)n_cand);
         atomicAdd(stats + 2, (unsigned long long)n_res);
         atomicAdd(stats + 3, (unsigned long long)n_steps);
+        atomicAdd(stats + 4, (unsigned long long)n_slots);
     }
 }
 
