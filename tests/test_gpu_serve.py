@@ -38,8 +38,13 @@ def test_alone_equals_mix(pool):
     srv = serve.Server(be, pool)
     states = srv.serve(jobs, arrivals)
     assert all(s.status == "done" for s in states), [s.error for s in states if s.error]
-    assert be.steps < len(jobs)                  # jobs shared launches
     assert sum(len(s.hr) for s in states) > 100
+    # with every job prepared and arrived at once, all share one launch
+    steps0 = be.steps
+    again = serve.Server(be, pool).serve(jobs, np.zeros(len(jobs)), realtime=False,
+                                         prepared={s.job.job_id: s.prep for s in states})
+    assert be.steps == steps0 + 1
+    assert [s.records.tobytes() for s in again] == [s.records.tobytes() for s in states]
     for st in states:
         alone = serve.JobState(st.job, 0.0, prep=st.prep)
         be.admit(alone)
