@@ -24,6 +24,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = "binary64 args checked/sec (exp, 2^40 slice); batched vs plain speedup, p99"
 PEAK_INT32_OPS = 256 * 64 * 2.4e9     # 256 CUs x 64 lanes x 2.4 GHz, one op/lane/clock
+PEAK_HBM = 8.0e12                     # bytes/s
+
+# The paper's own figures (Sec. 6, Tables 5-6): whole computation (tabulation
+# + search) of exp on binary64 [1, 2), Fermi C2070 + Xeon X5650 against the
+# same Xeon: context, not a target.
+PAPER_CONTEXT = {
+    "speedup_vs_1_core": 53.4, "speedup_vs_6_cores_12_ranks": 7.1,
+    "hardware": "NVIDIA Tesla C2070 (Fermi, 14 SMs) + Intel Xeon X5650 (6 cores, 2.67 GHz)",
+    "workload": "exp, binary64 binade [1, 2), directed (53, 2^-32) HR cases",
+}
 
 
 def parse():
@@ -41,7 +51,8 @@ def parse():
     p.add_argument("--prep-workers", type=int, default=16)
     p.add_argument("--probe", action="store_true",
                    help="profiling probe: a 1 GiB device copy, then 3 fused passes of the "
-                        "2^40 slice and 3 batched passes of the 16-job mix; no JSON")
+                        "2^40 slice, 3 tabulations of it and 3 batched passes of the 16-job "
+                        "mix; no JSON")
     return p.parse_args()
 
 
@@ -161,6 +172,7 @@ def main():
         "host_prep_s": prep_s,
         "end_to_end_args_per_s": args_total / (prep_s + ms_per_step / 1000),
     }
+    line["tabulation"] = bench_tabulation(spec, table, ctx, stream, args.steps)
     if not args.no_plain:
         tp = []
         for i in range(3):
@@ -176,6 +188,7 @@ def main():
         line["batch"] = bench_batch(args)
     if not args.no_serve:
         line["serving"] = bench_serve(args, pool)
+    line["paper_context"] = dict(PAPER_CONTEXT)
     if not args.no_cpu_baseline:
         from oracle import hr as ohr
         from oracle import native
@@ -192,9 +205,40 @@ def main():
     print(json.dumps(line))
 
 
+def bench_tabulation(spec, table, ctx, stream, steps):
+    """The tabulation stage alone (hr_tabulate: every piece's (a, b) of the
+    2^40 slice written to HBM), timed with HIP events on its stream.
+    Algorithmic bytes: the initial tables read once plus 16 bytes of (a, b)
+    written per piece."""
+    import torch
+
+    from paper_1211_3056_amd import _lib
+    pieces = spec.n_sub * spec.tau
+    a_out = torch.empty(pieces, dtype=torch.uint64, device=table.device)
+    b_out = torch.empty(pieces, dtype=torch.uint64, device=table.device)
+    run = lambda: _lib.hr_tabulate(ctx, table, spec.n_sub, spec.delta, spec.tau, spec.W,
+                                   a_out, b_out, stream)
+    run()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    for a, b in evs:
+        a.record(stream)
+        run()
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms = sum(a.elapsed_time(b) for a, b in evs) / steps
+    nbytes = table.numel() * 8 + pieces * 16
+    return {"kernel": f"k_tabulate<{spec.W // 32},{spec.delta}>", "kernel_ms": ms,
+            "pieces": pieces, "bytes": nbytes, "hbm_GBps": nbytes / (ms / 1000) / 1e9,
+            "hbm_frac": nbytes / (ms / 1000) / PEAK_HBM,
+            "pieces_per_s": pieces / (ms / 1000)}
+
+
 def probe():
     """Kernels for counter runs: a plain copy of known size (the reference
-    for scaling FETCH_SIZE / WRITE_SIZE), the fused pass, the batched pass."""
+    for scaling FETCH_SIZE / WRITE_SIZE), the fused pass, the tabulation
+    stage alone, the batched pass."""
     import torch
 
     import synth
@@ -210,6 +254,12 @@ def probe():
     dev = pipeline.upload(P)
     for _ in range(3):
         pipeline.run_fused(P, dev)
+    from paper_1211_3056_amd import _lib
+    a_out = torch.empty(spec.n_sub * spec.tau, dtype=torch.uint64, device="cuda")
+    b_out = torch.empty_like(a_out)
+    for _ in range(3):
+        _lib.hr_tabulate(api.context(), dev[0], spec.n_sub, spec.delta, spec.tau, spec.W,
+                         a_out, b_out)
     dp = batch.DevicePlan(batch.build_plan([batch.BatchJob(**d) for d in synth.config4()]))
     run = batch.Runner(dp)
     for _ in range(3):

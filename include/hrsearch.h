@@ -26,6 +26,15 @@
  *    placement, except in hr_pipeline whose result set is sorted by the
  *    caller; its order on the device is unspecified).
  *  - One context per host thread; calls on one context are not reentrant.
+ *  - A context owns a small fixed device area, allocated by hr_create and
+ *    never moved: the work-claim counter of hr_batch_run and the statistics
+ *    slots that hr_pipeline and hr_batch_run accumulate into before adding
+ *    them to the caller's stats array.  Launches through one context must
+ *    therefore not overlap on the device (use one stream per context, or
+ *    order the streams); a HIP graph captured from hr_pipeline or
+ *    hr_batch_run stays valid while its context lives.  hr_search also uses
+ *    a growable scratch area, which a later, larger hr_search on the same
+ *    context may move: do not capture hr_search in a graph.
  */
 #ifndef HRSEARCH_H
 #define HRSEARCH_H
@@ -221,12 +230,14 @@ hr_status hr_batch_run(hr_ctx* ctx, const uint64_t* pool, const hr_item* items, 
 /*
  * hr_quot_check -- diagnostic: the partial-quotient routine of the search,
  * out[i] = min(floor(num[i] / den[i]), cap) computed by the device code
- * (binary64 estimate + exact correction); out[i] = 2^64 - 1 where den[i] = 0.
- * For checking that routine against exact integer division.
- * Errors: HR_EINVAL for cap == 0 or cap >= 2^32, or null pointers.
+ * (binary64 reciprocal estimate + exact correction); out[i] = 2^64 - 1 where
+ * den[i] = 0.  If rem is non-null, rem[i] = num[i] - out[i] den[i] where
+ * out[i] < cap, and 2^64 - 1 elsewhere.  For checking that routine against
+ * exact integer division.  All arrays are device memory of n entries.
+ * Errors: HR_EINVAL for cap == 0 or cap >= 2^32, or null num/den/out.
  */
 hr_status hr_quot_check(hr_ctx* ctx, const uint64_t* num, const uint64_t* den, uint64_t cap,
-                        uint64_t* out, uint64_t n, void* stream);
+                        uint64_t* out, uint64_t* rem, uint64_t n, void* stream);
 
 #ifdef __cplusplus
 }

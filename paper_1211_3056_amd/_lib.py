@@ -72,7 +72,7 @@ def lib():
     L.hr_pipeline.restype = i32
     L.hr_pipeline.argtypes = [P, P, u32, u32, u32, u32, u32, P, P, P, u64, P, P, P]
     L.hr_quot_check.restype = i32
-    L.hr_quot_check.argtypes = [P, P, P, u64, P, u64, P]
+    L.hr_quot_check.argtypes = [P, P, P, u64, P, P, u64, P]
     L.hr_batch_run.restype = i32
     L.hr_batch_run.argtypes = [P, P, P, u32, u32, u32, u32, P, u64, P, P, P]
     _lib = L
@@ -165,6 +165,7 @@ def hr_batch_run(ctx, pool, items, n_items, width, degree, waves, out, cap, coun
                                               _stream(stream)))
 
 
-def hr_quot_check(ctx, num, den, cap, out, stream=None):
+def hr_quot_check(ctx, num, den, cap, out, rem=None, stream=None):
     _check("hr_quot_check", lib().hr_quot_check(ctx.handle, _p(num), _p(den), cap, _p(out),
+                                                _p(rem) if rem is not None else None,
                                                 num.numel(), _stream(stream)))

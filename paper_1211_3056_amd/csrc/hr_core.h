@@ -23,37 +23,62 @@ HR_HD uint64_t mulhi64(uint64_t a, uint64_t b) {
 
 HR_HD uint64_t umin(uint64_t a, uint64_t b) { return a < b ? a : b; }
 
-// Quotient estimate num/den in binary64 with relative error below 2^-50:
-// on the device one reciprocal (v_rcp_f64) refined by one Newton step, on
-// the host an IEEE division.
-HR_HD double fdiv_est(double num, double den) {
-#if defined(__HIP_DEVICE_COMPILE__)
-    double r = __builtin_amdgcn_rcp(den);
-    const double e = __builtin_fma(-den, r, 1.0);
-    r = __builtin_fma(r, e, r);
-    return num * r;
-#else
-    return num / den;
-#endif
+// Correctly rounded binary64 value of x: both 32-bit halves convert
+// exactly, and one fused multiply-add rounds their sum once.
+HR_HD double u64_to_f64(uint64_t x) {
+    return __builtin_fma((double)(uint32_t)(x >> 32), 4294967296.0, (double)(uint32_t)x);
 }
 
-// min(floor(num / den), cap) for den > 0, cap < 2^32.
+// Reciprocal of a divisor, reused by every quotient with that divisor: on
+// the device one v_rcp_f64 refined by one Newton step, on the host an IEEE
+// division.  Either way num * r is within a relative 2^-50 of num / den.
+struct Recip {
+    uint64_t den;
+    double r;
+};
+
+HR_HD Recip recip(uint64_t den) {
+    Recip R;
+    R.den = den;
+    const double dd = u64_to_f64(den);
+#if defined(__HIP_DEVICE_COMPILE__)
+    double r = __builtin_amdgcn_rcp(dd);
+    const double e = __builtin_fma(-dd, r, 1.0);
+    R.r = __builtin_fma(r, e, r);
+#else
+    R.r = 1.0 / dd;
+#endif
+    return R;
+}
+
+// min(floor(num / den), cap) for den > 0, cap < 2^32, and the remainder
+// num - q den when q < cap (unspecified when q = cap).
 // The binary64 estimate of the quotient of the (rounded) operands is within
 // 2^-10 of the true quotient whenever it is below cap + 2, so its floor is
-// off by at most one; one exact multiply-compare corrects it.  Larger
-// quotients saturate at cap: callers only need to know that they reach cap.
-HR_HD uint64_t quot_sat(uint64_t num, uint64_t den, uint64_t cap) {
-    const double e = fdiv_est((double)num, (double)den);
+// off by at most one; one exact multiply-compare corrects it and yields the
+// remainder.  Larger quotients saturate at cap: callers only need to know
+// that they reach cap.
+HR_HD uint32_t quot_rem(uint64_t num, const Recip& R, uint32_t cap, uint64_t& rem) {
+    const uint64_t den = R.den;
+    const double e = u64_to_f64(num) * R.r;
     const bool big = e > (double)cap + 2.0;
-    uint32_t k = (uint32_t)__builtin_fmin(e, 4294967295.0);
+    const uint32_t k = (uint32_t)__builtin_fmin(e, 4294967295.0);
     // k * den as a 96-bit product: lo (64 bits) and whether bits >= 64 are set
     const uint64_t t1 = (uint64_t)k * (uint32_t)den;
     const uint64_t t2 = (uint64_t)k * (uint32_t)(den >> 32) + (t1 >> 32);
     const uint64_t lo = (t2 << 32) | (uint32_t)t1;
     const bool over = (t2 >> 32) != 0 || lo > num;
-    const bool under = !over && num - lo >= den;
+    const uint64_t r0 = num - lo;
+    const bool under = !over && r0 >= den;
+    // r0 + den when over, r0 - den when under (masks, not branches)
+    rem = r0 + (den & (0 - (uint64_t)over)) - (den & (0 - (uint64_t)under));
     const uint64_t kk = (uint64_t)k - over + under;
-    return (big || kk >= cap) ? cap : kk;
+    return (big || kk >= cap) ? cap : (uint32_t)kk;
+}
+
+HR_HD uint32_t quot_sat(uint64_t num, uint64_t den, uint32_t cap) {
+    uint64_t rem;
+    return quot_rem(num, recip(den), cap, rem);
 }
 
 // floor(a / b) for 0 <= a < 2^53, 0 < b < 2^53 (indices): the correctly
@@ -84,84 +109,108 @@ HR_HD uint64_t idx_div(uint64_t a, uint64_t b) {
 // Requires a != 0, n >= 2 and all n points distinct (the period
 // 2^(64 - ctz(a)) of the sequence is >= n).
 struct Near {
-    uint64_t x;      // index of the closest point on the left of b
-    uint64_t d;      // its distance (b - x a) mod 2^64
-    uint64_t u;      // index in [1, n) of the point closest to 0 on the right
-    uint64_t v;      // index in [1, n) of the point closest to 0 on the left
+    uint32_t x;      // index of the closest point on the left of b
+    uint32_t u;      // index in [1, n) of the point closest to 0 on the right
+    uint32_t v;      // index in [1, n) of the point closest to 0 on the left
+    uint32_t steps;  // partial quotients computed
+    uint64_t d;      // distance of x: (b - x a) mod 2^64
     uint64_t alpha;  // u a mod 2^64      (gap right of each point)
     uint64_t beta;   // -v a mod 2^64     (gap left of each point)
-    uint32_t steps;  // partial quotients computed
 };
 
-HR_HD void closest_left(uint64_t a, uint64_t b, uint64_t n, Near& r) {
-    uint64_t p = a, q = 0;
-    uint64_t ip = 1, iq = 0, X = 0, d = b;
-    uint64_t u, v, alpha, beta;
+// n < 2^32.  Indices stay below n, so they are 32-bit; every quotient is
+// needed only up to n, so quot_rem saturates there.  A configuration that
+// would reach n points is the last one: the cut at n and the final
+// neighbours are worked out only there, so the loop body itself has no
+// index multiplications beyond the ones that grow ip and iq.
+HR_HD void closest_left(uint64_t a, uint64_t b, uint32_t n, Near& r) {
+    uint64_t p = a, q = 0, d = b;
+    uint32_t ip = 1, iq = 0, X = 0;
+    uint32_t u, v;
+    uint64_t alpha, beta;
     uint32_t steps = 1;
     // First quotient: q is 1 (2^64), which does not fit; floor(2^64 / a) is
     // floor((2^64 - 1) / a) plus one when a divides 2^64.
-    uint64_t k = quot_sat(~0ull, a, n);
-    if (k < n && (~0ull - k * a) == a - 1) k += 1;
+    const Recip Ra = recip(a);
+    uint64_t rem;
+    uint32_t k = quot_rem(~0ull, Ra, n, rem);
+    if (k < n && rem == a - 1) k += 1;
     {
         // b sits in the single interval [0, 1) whose left end has index 0
-        const uint64_t s = umin(umin(quot_sat(d, a, n), k), n - 1);
+        uint64_t rb;
+        const uint32_t s = (uint32_t)umin(umin(quot_rem(d, Ra, n, rb), k), n - 1);
         X = s;
-        d -= s * a;
+        d -= (uint64_t)s * a;
     }
-    if (1 + k >= n) {
+    if (1 + (uint64_t)k >= n) {
         u = 1;
         alpha = a;
-        v = umin(k, n - 1);
-        beta = 0 - v * a;
+        v = (uint32_t)umin(k, n - 1);
+        beta = 0 - (uint64_t)v * a;
     } else {
-        q = 0 - k * a;   // 2^64 mod a < a: the lengths now alternate, p > q first
+        q = 0 - (uint64_t)k * a;   // 2^64 mod a < a: the lengths now alternate, p > q first
         iq = k;
         // Each pass reduces p by q, then q by p (two partial quotients, as in
         // the paper's unrolled Alg. 4: which length shrinks alternates, so no
         // test on it is needed).  Where b sits is a select, not a branch.
+        // Both quotients of a half step share one divisor and so one
+        // reciprocal, and their remainders are the new length and the new
+        // distance of b.
         for (;;) {
             // ---- p > q: p-intervals (left ends < iq) get points at p - q, p - 2q, ..
             ++steps;
-            k = quot_sat(p, q, n);
-            {
-                const bool in_p = X < iq;
-                // the first new point at or left of b: s = ceil((p - d) / q)
-                const uint64_t s = quot_sat(in_p ? p - d - 1 : 0, q, n) + 1;
-                const bool take = in_p && s <= k && X + ip + s * iq < n;
-                X = take ? X + ip + s * iq : X;
-                d = take ? d - (p - s * q) : d;
-            }
-            if (ip + iq + k * iq >= n) {
-                const uint64_t su = umin(k, idx_div(n - 1 - ip, iq));
+            const Recip Rq = recip(q);
+            uint64_t rp, rb;
+            k = quot_rem(p, Rq, n, rp);
+            const bool in_p = X < iq;
+            // the first new point at or left of b: s = ceil((p - d) / q)
+            // = s1 + 1, and b's distance to it is q - 1 - rb
+            const uint32_t s1 = quot_rem(in_p ? p - d - 1 : 0, Rq, n, rb);
+            const uint64_t kiq = (uint64_t)k * iq;
+            if (ip + iq + kiq >= n) {
+                // last configuration: only points with index < n exist
+                const uint64_t s = (uint64_t)s1 + 1;
+                if (in_p && s <= k && X + ip + s * iq < n) {
+                    X += ip + (uint32_t)(s * iq);
+                    d = q - 1 - rb;
+                }
+                const uint32_t su = (uint32_t)umin(k, idx_div(n - 1 - ip, iq));
                 v = iq;
                 beta = q;
                 u = ip + su * iq;
-                alpha = p - su * q;
+                alpha = p - (uint64_t)su * q;
                 break;
             }
-            p -= k * q;
-            ip += k * iq;
+            const bool take = in_p && s1 < k;
+            X = take ? X + ip + (s1 + 1) * iq : X;
+            d = take ? q - 1 - rb : d;
+            p = rp;
+            ip += (uint32_t)kiq;
             // ---- q > p: q-intervals (left ends >= iq) get points at p, 2p, ..
             ++steps;
-            k = quot_sat(q, p, n);
-            {
-                const bool in_q = X >= iq;
-                uint64_t s = in_q ? umin(quot_sat(d, p, n), k) : 0;
-                // only points with index < n exist (matters in the last step)
+            const Recip Rp = recip(p);
+            uint64_t rq, rd;
+            k = quot_rem(q, Rp, n, rq);
+            const bool in_q = X >= iq;
+            // b's interval is shorter than q, so s2 = floor(d / p) <= k
+            const uint32_t s2 = quot_rem(in_q ? d : 0, Rp, n, rd);
+            const uint64_t kip = (uint64_t)k * ip;
+            if (ip + iq + kip >= n) {
+                uint64_t s = s2;
                 if (X + s * ip > n - 1) s = idx_div(n - 1 - X, ip);
-                X += s * ip;
+                X += (uint32_t)(s * ip);
                 d -= s * p;
-            }
-            if (ip + iq + k * ip >= n) {
-                const uint64_t sv = umin(k, idx_div(n - 1 - iq, ip));
+                const uint32_t sv = (uint32_t)umin(k, idx_div(n - 1 - iq, ip));
                 u = ip;
                 alpha = p;
                 v = iq + sv * ip;
-                beta = q - sv * p;
+                beta = q - (uint64_t)sv * p;
                 break;
             }
-            q -= k * p;
-            iq += k * ip;
+            X += s2 * ip;
+            d = in_q ? rd : d;
+            q = rq;
+            iq += (uint32_t)kip;
         }
     }
     r.x = X;
@@ -175,11 +224,11 @@ HR_HD void closest_left(uint64_t a, uint64_t b, uint64_t n, Near& r) {
 
 // Next point to the left of point x among the n points (three-distance
 // theorem: the gap left of a point is alpha, beta or alpha + beta).
-HR_HD void pred(const Near& r, uint64_t n, uint64_t& x, uint64_t& gap) {
+HR_HD void pred(const Near& r, uint32_t n, uint32_t& x, uint64_t& gap) {
     if (x >= r.u) {
         x -= r.u;
         gap = r.alpha;
-    } else if (x + r.v < n) {
+    } else if ((uint64_t)x + r.v < n) {
         x += r.v;
         gap = r.beta;
     } else {
@@ -190,7 +239,7 @@ HR_HD void pred(const Near& r, uint64_t n, uint64_t& x, uint64_t& gap) {
 
 // Resumable enumeration of the hits of one instance: every k < n with
 // (b - k a) mod 2^64 < D, produced by increasing distance (ties, which only
-// occur between repeated points, by increasing k).
+// occur between repeated points, by increasing k).  n < 2^32.
 //
 // Degenerate inputs: a = 0 puts every point at 0 and n = 1 has one point
 // (P = 1 distinct point); when the sequence has a period
@@ -198,15 +247,16 @@ HR_HD void pred(const Near& r, uint64_t n, uint64_t& x, uint64_t& gap) {
 // at k + m P.
 struct HitIter {
     Near r;
-    uint64_t n, P, D;
-    uint64_t x;        // current distinct point
-    uint64_t dist;     // its distance
-    uint64_t k;        // next repeat of x to report
-    uint64_t visited;  // distinct points reported so far
+    uint64_t D;
+    uint64_t dist;     // distance of the current distinct point
+    uint32_t n, P;
+    uint32_t x;        // current distinct point
+    uint32_t k;        // next repeat of x to report
+    uint32_t visited;  // distinct points reported so far
     bool done;
 };
 
-HR_HD void iter_init(HitIter& it, uint64_t a, uint64_t b, uint64_t n, uint64_t D,
+HR_HD void iter_init(HitIter& it, uint64_t a, uint64_t b, uint32_t n, uint64_t D,
                      uint32_t* steps = nullptr) {
     it.n = n;
     it.D = D;
@@ -220,7 +270,7 @@ HR_HD void iter_init(HitIter& it, uint64_t a, uint64_t b, uint64_t n, uint64_t D
     } else {
         it.P = n;
         const int tz = __builtin_ctzll(a);
-        if (tz > 32 && (1ull << (64 - tz)) < n) it.P = 1ull << (64 - tz);
+        if (tz > 32 && (1ull << (64 - tz)) < n) it.P = (uint32_t)(1ull << (64 - tz));
         closest_left(a, b, it.P, it.r);
         if (steps) *steps = it.r.steps;
         it.x = it.r.x;
@@ -235,8 +285,9 @@ HR_HD void iter_init(HitIter& it, uint64_t a, uint64_t b, uint64_t n, uint64_t D
 HR_HD bool iter_next(HitIter& it, uint64_t& k) {
     if (it.done) return false;
     k = it.k;
-    it.k += it.P;
-    if (it.k >= it.n) {          // all repeats of x reported: go left
+    if (it.P < it.n - it.k) {
+        it.k += it.P;
+    } else {                     // all repeats of x reported: go left
         if (it.visited == it.P) {
             it.done = true;
         } else {
@@ -256,7 +307,7 @@ HR_HD bool iter_next(HitIter& it, uint64_t& k) {
 
 // Calls emit(k) for every hit, in the order above; returns their number.
 template <class Emit>
-HR_HD uint64_t search_each(uint64_t a, uint64_t b, uint64_t n, uint64_t D, Emit&& emit,
+HR_HD uint64_t search_each(uint64_t a, uint64_t b, uint32_t n, uint64_t D, Emit&& emit,
                            uint32_t* steps = nullptr) {
     HitIter it;
     iter_init(it, a, b, n, D, steps);
@@ -269,7 +320,7 @@ HR_HD uint64_t search_each(uint64_t a, uint64_t b, uint64_t n, uint64_t D, Emit&
 }
 
 // Same, writing the first min(count, cap) hits to out (if non-null).
-HR_HD uint64_t search_one(uint64_t a, uint64_t b, uint64_t n, uint64_t D,
+HR_HD uint64_t search_one(uint64_t a, uint64_t b, uint32_t n, uint64_t D,
                           uint32_t* out, uint64_t cap) {
     uint64_t m = 0;
     return search_each(a, b, n, D, [&](uint64_t k) {

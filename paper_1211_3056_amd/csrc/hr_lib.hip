@@ -23,8 +23,11 @@
 
 struct hr_ctx {
     int device;
-    void* scratch;
+    void* scratch;          // growable: block sums of hr_search
     size_t scratch_bytes;
+    void* fixed;            // allocated once by hr_create, never moved (so a
+                            // captured graph may keep pointing at it): the
+                            // work-claim counter, then the statistics slots
 };
 
 namespace {
@@ -213,29 +216,58 @@ __device__ __forceinline__ void row_step(hr::Word<L>* v) {
 
 // ---------------------------------------------------------------- tabulate
 
+constexpr uint32_t kMaxNu = 16;   // pieces per lane (pick_nu never exceeds it)
+
+// One wave: lane l expands its packet of cnt <= nu consecutive pieces.  The
+// outputs of a wave's lanes form one contiguous range of the flattened
+// (sub-interval, piece) order (a lane is followed by the next packet of its
+// sub-interval, or by the first packet of the next one), so the pieces are
+// staged in LDS and written back as coalesced runs rather than as 64
+// strided streams.  LDS index of range position e: e + e / 16 (a pad word
+// every 16 entries keeps the strided staging writes off a single bank).
 template <int L, int DEG>
-__global__ __launch_bounds__(kBlock) void k_tabulate(const uint64_t* __restrict__ table,
-                                                    uint32_t n_sub, uint32_t tau, uint32_t nu,
-                                                    uint64_t* __restrict__ a_out,
-                                                    uint64_t* __restrict__ b_out) {
-    const uint64_t gid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+__global__ __launch_bounds__(64) void k_tabulate(const uint64_t* __restrict__ table,
+                                                uint32_t n_sub, uint32_t tau, uint32_t nu,
+                                                uint64_t* __restrict__ a_out,
+                                                uint64_t* __restrict__ b_out) {
+    constexpr uint32_t kStage = 64 * kMaxNu + 64 * kMaxNu / 16;
+    __shared__ uint64_t s_a[kStage];
+    __shared__ uint64_t s_b[kStage];
+    const int lane = threadIdx.x;
+    const uint64_t gid = (uint64_t)blockIdx.x * 64 + lane;
     const uint64_t per_sub = (tau + nu - 1) / nu;
-    if (gid >= (uint64_t)n_sub * per_sub) return;
-    const uint64_t sub = gid / per_sub;
-    const uint64_t i0 = (gid % per_sub) * nu;
-    const uint32_t cnt = (uint32_t)hr::umin(nu, tau - i0);
-    const uint64_t* T = table + sub * n_entries(DEG) * (L / 2);
-    hr::Word<L> v0[DEG + 1], v1[DEG];
-    uint32_t cb[DEG][4];
-    binom_limbs<DEG>(i0, cb);
-    row_start<L, DEG, 0>(T, cb, v0);
-    row_start<L, DEG, 1>(T, cb, v1);
-    const uint64_t base = sub * tau + i0;
-    for (uint32_t s = 0; s < cnt; ++s) {
-        b_out[base + s] = top64(v0[0]);
-        a_out[base + s] = neg_top64(v1[0]);
-        row_step<L, DEG + 1>(v0);
-        row_step<L, DEG>(v1);
+    const bool active = gid < (uint64_t)n_sub * per_sub;   // lane 0 always is
+    uint64_t sub = 0, i0 = 0, base = 0;
+    uint32_t cnt = 0;
+    if (active) {
+        sub = gid / per_sub;
+        i0 = (gid % per_sub) * nu;
+        cnt = (uint32_t)hr::umin(nu, tau - i0);
+        base = sub * tau + i0;
+    }
+    const uint64_t wbase = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(base >> 32)) << 32) |
+                           (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)base);
+    const uint32_t total = (uint32_t)wave_sum(cnt);   // <= 64 nu
+    if (active) {
+        const uint64_t* T = table + sub * n_entries(DEG) * (L / 2);
+        hr::Word<L> v0[DEG + 1], v1[DEG];
+        uint32_t cb[DEG][4];
+        binom_limbs<DEG>(i0, cb);
+        row_start<L, DEG, 0>(T, cb, v0);
+        row_start<L, DEG, 1>(T, cb, v1);
+        const uint32_t e0 = (uint32_t)(base - wbase);
+        for (uint32_t s = 0; s < cnt; ++s) {
+            const uint32_t e = e0 + s;
+            s_b[e + e / 16] = top64(v0[0]);
+            s_a[e + e / 16] = neg_top64(v1[0]);
+            row_step<L, DEG + 1>(v0);
+            row_step<L, DEG>(v1);
+        }
+    }
+    __syncthreads();
+    for (uint32_t e = lane; e < total; e += 64) {
+        b_out[wbase + e] = s_b[e + e / 16];
+        a_out[wbase + e] = s_a[e + e / 16];
     }
 }
 
@@ -408,10 +440,19 @@ __device__ __forceinline__ void fused_wave(
     }
 }
 
-__device__ __forceinline__ void flush_stats(unsigned long long* stats, uint64_t n_pieces,
+// Statistics are summed per wave, then added into one of kStatSlots
+// 64-byte slots picked by workgroup index, so that thousands of waves do
+// not queue on the same few addresses (atomics on one line are serialised:
+// a single line cost up to a fifth of a launch).  k_stats_flush adds the
+// slots into the caller's array afterwards and clears them.
+constexpr int kStatSlots = 256;
+constexpr int kStatFields = 8;
+
+__device__ __forceinline__ void flush_stats(unsigned long long* slots, uint64_t n_pieces,
                                             uint64_t n_cand, uint64_t n_res, uint64_t n_steps,
                                             uint64_t n_slots) {
-    if (!stats) return;
+    if (!slots) return;
+    unsigned long long* stats = slots + (blockIdx.x % kStatSlots) * kStatFields;
     n_pieces = wave_sum(n_pieces);
     n_cand = wave_sum(n_cand);
     n_res = wave_sum(n_res);
@@ -543,12 +584,48 @@ __global__ __launch_bounds__(64) void k_items(
 
 __global__ void k_zero_u32(unsigned int* p) { *p = 0u; }
 
+// One wave: stats[f] += sum over slots of slot[f]; the slots are left zero.
+// All loads are issued before any reduction, so the kernel costs about one
+// memory round trip.
+__global__ __launch_bounds__(64) void k_stats_flush(unsigned long long* __restrict__ slots,
+                                                   unsigned long long* __restrict__ stats) {
+    uint64_t v[kStatFields];
+#pragma unroll
+    for (int f = 0; f < kStatFields; ++f) v[f] = 0;
+#pragma unroll
+    for (int i = 0; i < kStatSlots / 64; ++i) {
+        unsigned long long* s = slots + (i * 64 + threadIdx.x) * kStatFields;
+#pragma unroll
+        for (int f = 0; f < kStatFields; ++f) v[f] += s[f];
+    }
+#pragma unroll
+    for (int i = 0; i < kStatSlots / 64; ++i) {
+        unsigned long long* s = slots + (i * 64 + threadIdx.x) * kStatFields;
+#pragma unroll
+        for (int f = 0; f < kStatFields; ++f) s[f] = 0;
+    }
+#pragma unroll
+    for (int f = 0; f < kStatFields; ++f) v[f] = wave_sum(v[f]);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int f = 0; f < kStatFields; ++f)
+            if (v[f]) atomicAdd(stats + f, (unsigned long long)v[f]);
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_quot_check(const uint64_t* __restrict__ num,
                                                       const uint64_t* __restrict__ den,
                                                       uint64_t cap, uint64_t* __restrict__ out,
-                                                      uint64_t n) {
+                                                      uint64_t* __restrict__ rem, uint64_t n) {
     const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) out[i] = den[i] ? hr::quot_sat(num[i], den[i], cap) : ~0ull;
+    if (i >= n) return;
+    uint64_t q = ~0ull, r = ~0ull;
+    if (den[i]) {
+        q = hr::quot_rem(num[i], hr::recip(den[i]), (uint32_t)cap, r);
+        if (q >= cap) r = ~0ull;
+    }
+    out[i] = q;
+    if (rem) rem[i] = r;
 }
 
 // ---------------------------------------------------------------- host side
@@ -557,6 +634,27 @@ hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 hr_status launched() {
     return hipGetLastError() == hipSuccess ? HR_OK : HR_EDEVICE;
+}
+
+// Layout of the context's fixed device area.
+constexpr size_t kClaimOffset = 0;      // uint32 work-claim counter
+constexpr size_t kSlotsOffset = 256;    // kStatSlots x kStatFields uint64
+constexpr size_t kFixedBytes = kSlotsOffset + kStatSlots * kStatFields * sizeof(uint64_t);
+
+unsigned int* claim_counter(hr_ctx* ctx) {
+    return (unsigned int*)((char*)ctx->fixed + kClaimOffset);
+}
+
+// Statistics slots of the context when the caller wants statistics, else null.
+unsigned long long* stat_slots(hr_ctx* ctx, uint64_t* stats) {
+    return stats ? (unsigned long long*)((char*)ctx->fixed + kSlotsOffset) : nullptr;
+}
+
+// After a launch that wrote the slots: add them into stats, clear them.
+hr_status flush_stat_slots(hr_ctx* ctx, uint64_t* stats, hipStream_t st) {
+    if (!stats) return HR_OK;
+    k_stats_flush<<<1, 64, 0, st>>>(stat_slots(ctx, stats), (unsigned long long*)stats);
+    return launched();
 }
 
 hr_status ensure_scratch(hr_ctx* ctx, size_t bytes) {
@@ -649,6 +747,16 @@ hr_status hr_create(hr_ctx** out, int device) {
     hr_ctx* c = (hr_ctx*)calloc(1, sizeof(hr_ctx));
     if (!c) return HR_ENOMEM;
     c->device = device;
+    if (hipMalloc(&c->fixed, kFixedBytes) != hipSuccess) {
+        free(c);
+        return HR_ENOMEM;
+    }
+    if (hipMemset(c->fixed, 0, kFixedBytes) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
+        (void)hipFree(c->fixed);
+        free(c);
+        return HR_EDEVICE;
+    }
     *out = c;
     return HR_OK;
 }
@@ -656,10 +764,9 @@ hr_status hr_create(hr_ctx** out, int device) {
 hr_status hr_destroy(hr_ctx* ctx) {
     if (!ctx) return HR_OK;
     (void)hipSetDevice(ctx->device);
-    if (ctx->scratch) {
-        (void)hipDeviceSynchronize();
-        (void)hipFree(ctx->scratch);
-    }
+    (void)hipDeviceSynchronize();
+    if (ctx->scratch) (void)hipFree(ctx->scratch);
+    if (ctx->fixed) (void)hipFree(ctx->fixed);
     free(ctx);
     return HR_OK;
 }
@@ -703,11 +810,12 @@ hr_status hr_tabulate(hr_ctx* ctx, const uint64_t* table, uint32_t n_sub, uint32
     if (hipSetDevice(ctx->device) != hipSuccess) return HR_EDEVICE;
     hipStream_t st = as_stream(stream);
     const uint32_t nu = pick_nu(n_sub, tau);
+    if (nu > kMaxNu) return HR_EINVAL;
     const uint64_t lanes = (uint64_t)n_sub * ((tau + nu - 1) / nu);
-    const uint64_t blocks = (lanes + kBlock - 1) / kBlock;
+    const uint64_t blocks = (lanes + 63) / 64;
     if (blocks > 0xffffffffull) return HR_EINVAL;
     HR_DISPATCH(width_bits, degree,
-                (k_tabulate<L_, D_><<<dim3((uint32_t)blocks), dim3(kBlock), 0, st>>>(
+                (k_tabulate<L_, D_><<<dim3((uint32_t)blocks), dim3(64), 0, st>>>(
                     table, n_sub, tau, nu, a_out, b_out)));
     return launched();
 }
@@ -750,12 +858,13 @@ hr_status hr_pipeline(hr_ctx* ctx, const uint64_t* table, uint32_t n_sub, uint32
     HR_DISPATCH(width_bits, degree,
                 (k_pipeline<L_, D_><<<dim3((uint32_t)blocks), dim3(64), 0, st>>>(
                     table, n_sub, tau, nu, N, win, thr, out, cap,
-                    (unsigned long long*)count, (unsigned long long*)stats)));
-    return launched();
+                    (unsigned long long*)count, stat_slots(ctx, stats))));
+    const hr_status s = launched();
+    return s != HR_OK ? s : flush_stat_slots(ctx, stats, st);
 }
 
 hr_status hr_quot_check(hr_ctx* ctx, const uint64_t* num, const uint64_t* den, uint64_t cap,
-                        uint64_t* out, uint64_t n, void* stream) {
+                        uint64_t* out, uint64_t* rem, uint64_t n, void* stream) {
     if (!ctx || cap == 0 || cap >= (1ull << 32)) return HR_EINVAL;
     if (n == 0) return HR_OK;
     if (!num || !den || !out) return HR_EINVAL;
@@ -763,7 +872,7 @@ hr_status hr_quot_check(hr_ctx* ctx, const uint64_t* num, const uint64_t* den, u
     const uint64_t blocks = (n + kBlock - 1) / kBlock;
     if (blocks > 0xffffffffull) return HR_EINVAL;
     k_quot_check<<<dim3((uint32_t)blocks), dim3(kBlock), 0, as_stream(stream)>>>(num, den, cap,
-                                                                                 out, n);
+                                                                                 out, rem, n);
     return launched();
 }
 
@@ -776,11 +885,10 @@ hr_status hr_batch_run(hr_ctx* ctx, const uint64_t* pool, const hr_item* items, 
     if (!pool || !items || (cap > 0 && !out)) return HR_EINVAL;
     if (hipSetDevice(ctx->device) != hipSuccess) return HR_EDEVICE;
     hipStream_t st = as_stream(stream);
-    hr_status s = ensure_scratch(ctx, 256);
-    if (s != HR_OK) return s;
-    unsigned int* next = (unsigned int*)ctx->scratch;
+    hr_status s = HR_OK;
+    unsigned int* next = claim_counter(ctx);
     unsigned long long* cnt = (unsigned long long*)count;
-    unsigned long long* sts = (unsigned long long*)stats;
+    unsigned long long* sts = stat_slots(ctx, stats);
     if (waves > 0) {
         k_zero_u32<<<1, 1, 0, st>>>(next);
         if ((s = launched()) != HR_OK) return s;
@@ -793,7 +901,8 @@ hr_status hr_batch_run(hr_ctx* ctx, const uint64_t* pool, const hr_item* items, 
                     (k_items<L_, D_, false><<<dim3(n_items), dim3(64), 0, st>>>(
                         pool, items, n_items, next, out, cap, cnt, sts)));
     }
-    return launched();
+    if ((s = launched()) != HR_OK) return s;
+    return flush_stat_slots(ctx, stats, st);
 }
 
 }  // extern "C"

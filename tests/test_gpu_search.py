@@ -173,8 +173,10 @@ def test_device_quotient_routine_exact():
     den_t = api.to_dev(np.array(dens, np.uint64), torch.uint64)
     for cap in (1, 65536, (1 << 32) - 1, 3000000000):
         out = torch.empty(len(nums), dtype=torch.uint64, device="cuda")
-        _lib.hr_quot_check(api.context(), num_t, den_t, cap, out)
-        got = out.cpu().numpy()
+        rem = torch.empty(len(nums), dtype=torch.uint64, device="cuda")
+        _lib.hr_quot_check(api.context(), num_t, den_t, cap, out, rem)
+        got, got_r = out.cpu().numpy(), rem.cpu().numpy()
         want = np.array([min(n // d, cap) for n, d in zip(nums, dens)], np.uint64)
-        bad = np.nonzero(got != want)[0]
+        want_r = np.array([n % d if n // d < cap else M - 1 for n, d in zip(nums, dens)], np.uint64)
+        bad = np.nonzero((got != want) | (got_r != want_r))[0]
         assert bad.size == 0, [(nums[i], dens[i], cap, int(got[i]), int(want[i])) for i in bad[:5]]
