@@ -385,27 +385,29 @@ HR_HD void wmac128(Word<L>& acc, const Word<L>& x, const uint32_t m[4]) {
     }
 }
 
-// Binomials C(x, 1..J) as exact 128-bit integers, incrementally:
+// C(x, j) from c = C(x, j - 1), 1 <= j <= 6, as an exact 128-bit integer:
 // C(x, j) = C(x, j-1) (x - j + 1) / j, the division being exact (by 2 and 4
 // a shift, by 3, 5 and 6 a multiplication by the inverse of the odd part
-// modulo 2^128).  Valid while x^J < 2^128.
-HR_HD void binoms128(uint64_t x, int J, unsigned __int128* c) {
-    // inverses of 3, 5, 15 and 45 modulo 2^128
+// modulo 2^128).  Valid while x^j < 2^128.  For j = x + 1 the factor
+// x - j + 1 is zero, so every later step stays zero without a test.
+HR_HD unsigned __int128 binom_step(unsigned __int128 c, uint64_t x, int j) {
+    // inverses of 3 and 5 modulo 2^128
     const unsigned __int128 inv3 = ((unsigned __int128)0xaaaaaaaaaaaaaaaaull << 64) | 0xaaaaaaaaaaaaaaabull;
     const unsigned __int128 inv5 = ((unsigned __int128)0xccccccccccccccccull << 64) | 0xcccccccccccccccdull;
-    unsigned __int128 v = x;
-    c[0] = v;                                        // C(x, 1)
-    for (int j = 2; j <= J; ++j) {
-        if (x + 1 < (uint64_t)j) { c[j - 1] = 0; continue; }
-        v = v * (unsigned __int128)(x - (uint64_t)(j - 1));
-        // v = x (x-1) .. (x-j+1) / (j-1)!  ->  divide by j
-        if (j == 2) v >>= 1;
-        else if (j == 3) v *= inv3;
-        else if (j == 4) v >>= 2;
-        else if (j == 5) v *= inv5;
-        else if (j == 6) { v >>= 1; v *= inv3; }
-        c[j - 1] = v;
-    }
+    if (j == 1) return x;
+    unsigned __int128 v = c * (unsigned __int128)(x - (uint64_t)(j - 1));   // = j C(x, j)
+    if (j == 2) v >>= 1;
+    else if (j == 3) v *= inv3;
+    else if (j == 4) v >>= 2;
+    else if (j == 5) v *= inv5;
+    else if (j == 6) { v >>= 1; v *= inv3; }
+    return v;
+}
+
+// Binomials C(x, 1..J), c[j-1] = C(x, j).
+HR_HD void binoms128(uint64_t x, int J, unsigned __int128* c) {
+    unsigned __int128 v = 1;
+    for (int j = 1; j <= J; ++j) c[j - 1] = v = binom_step(v, x, j);
 }
 
 HR_HD unsigned __int128 binom128(uint64_t x, int j) {

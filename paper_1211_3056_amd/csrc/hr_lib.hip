@@ -337,22 +337,84 @@ struct Origin {
     const uint64_t* thr;
 };
 
+// Register layout of the fused pass.  Row j of the difference table at a
+// piece is the vector Delta^l r_j, l = 0..DEG-j.  Its top entry
+// Delta^(DEG-j) r_j is the leading difference of a polynomial of degree
+// DEG - j in the piece index, hence the same for every piece of a
+// sub-interval: it is kept once per wave in LDS (s_top), and registers hold
+// only the DEG - j lower entries of each row ("low" entries).
+__host__ __device__ constexpr int n_low(int deg) { return deg * (deg + 1) / 2; }
+__host__ __device__ constexpr int low_entry(int deg, int j, int l) {   // l < deg - j
+    return j * deg - j * (j - 1) / 2 + l;
+}
+
+// Low entries of row J at piece i0 (straightforward shift, Sec. 5.2).
+template <int L, int DEG, int J>
+__device__ __forceinline__ void row_start_low(const uint64_t* __restrict__ T,
+                                              const uint32_t (*c)[4], hr::Word<L>* v) {
+#pragma unroll
+    for (int l = 0; l < DEG - J; ++l) {
+        load_word<L>(T + (size_t)entry(DEG, J, l) * (L / 2), v[l]);
+#pragma unroll
+        for (int m = 1; l + m <= DEG - J; ++m) {
+            hr::Word<L> t;
+            load_word<L>(T + (size_t)entry(DEG, J, l + m) * (L / 2), t);
+            hr::wmac128(v[l], t, c[m - 1]);
+        }
+    }
+}
+
+template <int L>
+__device__ __forceinline__ void lds_word(const uint32_t* p, hr::Word<L>& w) {
+#pragma unroll
+    for (int i = 0; i < L; ++i) w.w[i] = p[i];
+}
+
+// One tabulated-difference step of the LEN low entries of a row whose top
+// entry is top (Fig. 7).
+template <int L, int LEN>
+__device__ __forceinline__ void row_step_low(hr::Word<L>* v, const uint32_t* top) {
+    if constexpr (LEN > 0) {
+#pragma unroll
+        for (int l = 0; l + 1 < LEN; ++l) hr::wadd(v[l], v[l + 1]);
+        hr::Word<L> t;
+        lds_word<L>(top, t);
+        hr::wadd(v[LEN - 1], t);
+    }
+}
+
+// Cooperative load of the top entries of one sub-interval's table into
+// s_top[j L + w] (limb w of Delta^(DEG-j) r_j).  Whole wave; ends with a
+// barrier.
+template <int L, int DEG>
+__device__ __forceinline__ void load_top(const uint64_t* __restrict__ T, uint32_t* s_top) {
+    __syncthreads();   // previous readers of s_top are done
+    const int t = threadIdx.x;
+    if (t < (DEG + 1) * L) {
+        const int j = t / L, w = t % L;
+        const uint64_t word = T[(size_t)entry(DEG, j, DEG - j) * (L / 2) + w / 2];
+        s_top[t] = (uint32_t)(word >> (32 * (w & 1)));
+    }
+    __syncthreads();
+}
+
 // The per-wave body of the fused pass.  Each lane owns a packet of up to nu
-// consecutive pieces (cnt of them live, starting at piece p_begin) and keeps
-// the full difference table of all rows r_0..r_DEG in registers, advanced by
-// one tabulated-difference step per piece.  For its current piece a lane runs
-// the exact degree-1 search; candidates are compacted into an LDS queue
-// (ballot + mbcnt) next to the piece rows, and all 64 lanes then recheck
-// queued candidates in parallel, so the uneven number of candidates per
-// piece does not idle lanes.  origin(src, s) names the piece of lane src at
-// step s.  Must be called by the whole wave (uniform nu).
+// consecutive pieces (cnt of them live, starting at piece p_begin) of the
+// wave's sub-interval and keeps the low entries of its difference table in
+// registers, advanced by one tabulated-difference step per piece.  For its
+// current piece a lane runs the exact degree-1 search; candidates are
+// compacted into an LDS queue (ballot + mbcnt) next to the piece rows, and
+// all 64 lanes then recheck queued candidates in parallel, so the uneven
+// number of candidates per piece does not idle lanes.  origin(src, s) names
+// the piece of lane src at step s.  Must be called by the whole wave
+// (uniform nu).
 template <int L, int DEG, class OriginFn>
 __device__ __forceinline__ void fused_wave(
-    hr::Word<L>* v, bool active, uint32_t cnt, uint32_t nu, uint64_t p_begin, uint32_t N,
-    uint32_t last_piece, uint32_t last_N, uint64_t wlo, uint64_t wd, uint32_t* s_rows,
-    uint32_t* s_qlane, uint32_t* s_qk, OriginFn&& origin, hr_result* __restrict__ out,
-    uint64_t cap, unsigned long long* __restrict__ count, uint64_t& n_pieces, uint64_t& n_cand,
-    uint64_t& n_res, uint64_t& n_steps, uint64_t& n_slots) {
+    hr::Word<L>* v, const uint32_t* s_top, bool active, uint32_t cnt, uint32_t nu,
+    uint64_t p_begin, uint32_t N, uint32_t last_piece, uint32_t last_N, uint64_t wlo, uint64_t wd,
+    uint32_t* s_rows, uint32_t* s_qlane, uint32_t* s_qk, OriginFn&& origin,
+    hr_result* __restrict__ out, uint64_t cap, unsigned long long* __restrict__ count,
+    uint64_t& n_pieces, uint64_t& n_cand, uint64_t& n_res, uint64_t& n_steps, uint64_t& n_slots) {
     const int lane = threadIdx.x;
     for (uint32_t s = 0; s < nu; ++s) {
         const bool live = active && s < cnt;
@@ -362,8 +424,15 @@ __device__ __forceinline__ void fused_wave(
         if (live) {
             const uint64_t piece = p_begin + s;
             const uint32_t n = (piece == last_piece) ? last_N : N;
-            const uint64_t bb = top64(v[entry(DEG, 0, 0)]) - wlo;
-            const uint64_t aa = neg_top64(v[entry(DEG, 1, 0)]);
+            const uint64_t bb = top64(v[low_entry(DEG, 0, 0)]) - wlo;
+            uint64_t aa;
+            if constexpr (DEG >= 2) {
+                aa = neg_top64(v[low_entry(DEG, 1, 0)]);
+            } else {
+                hr::Word<L> r1;
+                lds_word<L>(s_top + L, r1);
+                aa = neg_top64(r1);
+            }
             hr::iter_init(it, aa, bb, n, wd, &steps);
             ++n_pieces;
             n_steps += steps;
@@ -373,12 +442,12 @@ __device__ __forceinline__ void fused_wave(
             const uint32_t nlive = (uint32_t)__popcll(__ballot(live));
             if (lane == 0) n_slots += (uint64_t)wmax * nlive;
         }
-        if (!it.done) {   // only pieces with candidates publish their rows
+        if (!it.done) {   // only pieces with candidates publish their rows r_0..r_(DEG-1)
 #pragma unroll
-            for (int j = 0; j <= DEG; ++j)
+            for (int j = 0; j < DEG; ++j)
 #pragma unroll
                 for (int w = 0; w < L; ++w)
-                    s_rows[(j * L + w) * 64 + lane] = v[entry(DEG, j, 0)].w[w];
+                    s_rows[(j * L + w) * 64 + lane] = v[low_entry(DEG, j, 0)].w[w];
         }
         for (;;) {
             uint32_t qn = 0;
@@ -398,18 +467,25 @@ __device__ __forceinline__ void fused_wave(
             for (uint32_t e = lane; e < qn; e += 64) {   // drain
                 const uint32_t src = s_qlane[e];
                 const uint64_t k = s_qk[e];
+                // P_i(k) = sum_j r_j C(k, j); C(k, j) built up one j at a time
                 hr::Word<L> V;
 #pragma unroll
                 for (int w = 0; w < L; ++w) V.w[w] = s_rows[w * 64 + src];
-                uint32_t cb[DEG][4];
-                binom_limbs<DEG>(k, cb);
-#pragma unroll
-                for (int j = 1; j <= DEG; ++j) {
+                unsigned __int128 ck = 1;
+                static_for<1, DEG + 1>([&](auto J) {
+                    constexpr int j = decltype(J)::value;
+                    ck = hr::binom_step(ck, k, j);
                     hr::Word<L> r;
+                    if constexpr (j < DEG) {
 #pragma unroll
-                    for (int w = 0; w < L; ++w) r.w[w] = s_rows[(j * L + w) * 64 + src];
-                    hr::wmac128(V, r, cb[j - 1]);
-                }
+                        for (int w = 0; w < L; ++w) r.w[w] = s_rows[(j * L + w) * 64 + src];
+                    } else {
+                        lds_word<L>(s_top + DEG * L, r);
+                    }
+                    uint32_t m[4];
+                    hr::split128(ck, m);
+                    hr::wmac128(V, r, m);
+                });
                 const uint64_t t = top64(V);
                 const Origin o = origin(src, s);
                 const uint8_t cls = classify<L>(t, o.thr);
@@ -433,10 +509,27 @@ __device__ __forceinline__ void fused_wave(
             __syncthreads();
             if (__ballot(!it.done) == 0) break;
         }
-        static_for<0, DEG + 1>([&](auto J) {
+        static_for<0, DEG>([&](auto J) {
             constexpr int j = decltype(J)::value;
-            row_step<L, DEG - j + 1>(v + entry(DEG, j, 0));
+            row_step_low<L, DEG - j>(v + low_entry(DEG, j, 0), s_top + j * L);
         });
+    }
+}
+
+// Low entries of every row at piece i0 of table T (inactive lanes: zero).
+template <int L, int DEG>
+__device__ __forceinline__ void start_low(const uint64_t* __restrict__ T, uint64_t i0, bool active,
+                                          hr::Word<L>* v) {
+    if (active) {
+        uint32_t cb[DEG][4];
+        binom_limbs<DEG>(i0, cb);
+        static_for<0, DEG>([&](auto J) {
+            constexpr int j = decltype(J)::value;
+            row_start_low<L, DEG, j>(T, cb, v + low_entry(DEG, j, 0));
+        });
+    } else {
+#pragma unroll
+        for (int e = 0; e < n_low(DEG); ++e) hr::wzero(v[e]);
     }
 }
 
@@ -467,68 +560,58 @@ __device__ __forceinline__ void flush_stats(unsigned long long* slots, uint64_t 
     }
 }
 
-// Whole sub-intervals of one uniform job (hr_pipeline): lane gid owns packet
-// gid of the flattened (sub-interval, packet) grid.
+// Whole sub-intervals of one uniform job (hr_pipeline).  Sub-interval s has
+// per_sub = ceil(tau / nu) packets, handled by wps = ceil(per_sub / 64)
+// consecutive waves (one workgroup each), so every wave works inside one
+// sub-interval: packet (b mod wps) 64 + lane of sub-interval b / wps.
 template <int L, int DEG>
 __global__ __launch_bounds__(64) void k_pipeline(
-    const uint64_t* __restrict__ table, uint32_t n_sub, uint32_t tau, uint32_t nu, uint32_t N,
-    const uint64_t* __restrict__ win, const uint64_t* __restrict__ thr, hr_result* __restrict__ out,
-    uint64_t cap, unsigned long long* __restrict__ count, unsigned long long* __restrict__ stats) {
-    constexpr int E = n_entries(DEG);
-    __shared__ uint32_t s_rows[(DEG + 1) * L * 64];   // word-major: [(j L + w) * 64 + lane]
+    const uint64_t* __restrict__ table, uint32_t n_sub, uint32_t tau, uint32_t nu, uint32_t wps,
+    uint32_t N, const uint64_t* __restrict__ win, const uint64_t* __restrict__ thr,
+    hr_result* __restrict__ out, uint64_t cap, unsigned long long* __restrict__ count,
+    unsigned long long* __restrict__ stats) {
+    __shared__ uint32_t s_rows[DEG * L * 64];   // word-major: [(j L + w) * 64 + lane]
+    __shared__ uint32_t s_top[(DEG + 1) * L];
     __shared__ uint32_t s_qlane[kQueue];
     __shared__ uint32_t s_qk[kQueue];
     const int lane = threadIdx.x;
-    const uint64_t per_sub = (tau + nu - 1) / nu;
-    const uint64_t gid = (uint64_t)blockIdx.x * 64 + lane;
-    const bool active = gid < (uint64_t)n_sub * per_sub;
-    uint64_t sub = 0, i0 = 0;
-    uint32_t cnt = 0;
-    if (active) {
-        sub = gid / per_sub;
-        i0 = (gid % per_sub) * nu;
-        cnt = (uint32_t)hr::umin(nu, tau - i0);
-    }
-    hr::Word<L> v[E];
-    if (active) {
-        const uint64_t* T = table + sub * E * (L / 2);
-        uint32_t cb[DEG][4];
-        binom_limbs<DEG>(i0, cb);
-        static_for<0, DEG + 1>([&](auto J) {
-            row_start<L, DEG, decltype(J)::value>(T, cb, v + entry(DEG, decltype(J)::value, 0));
-        });
-    } else {
-#pragma unroll
-        for (int e = 0; e < E; ++e) hr::wzero(v[e]);
-    }
-    const uint64_t wlo = active ? win[2 * sub] : 0;
-    const uint64_t wd = active ? win[2 * sub + 1] : 0;
+    const uint32_t per_sub = (tau + nu - 1) / nu;
+    const uint32_t sub = blockIdx.x / wps;                 // < n_sub (grid = n_sub wps)
+    const uint32_t packet0 = (blockIdx.x % wps) * 64;
+    const uint32_t packet = packet0 + lane;
+    const bool active = packet < per_sub;
+    const uint64_t i0 = (uint64_t)packet * nu;
+    const uint32_t cnt = active ? (uint32_t)hr::umin(nu, tau - i0) : 0;
+    const uint64_t* T = table + (uint64_t)sub * n_entries(DEG) * (L / 2);
+    load_top<L, DEG>(T, s_top);
+    hr::Word<L> v[n_low(DEG)];
+    start_low<L, DEG>(T, i0, active, v);
+    const uint64_t wlo = win[2 * (uint64_t)sub];
+    const uint64_t wd = win[2 * (uint64_t)sub + 1];
     uint64_t n_pieces = 0, n_cand = 0, n_res = 0, n_steps = 0, n_slots = 0;
     auto origin = [&](uint32_t src, uint32_t s) {
-        const uint64_t g = (uint64_t)blockIdx.x * 64 + src;
-        const uint64_t ssub = g / per_sub;
         Origin o;
         o.job = 0;
-        o.sub = (uint32_t)ssub;
-        o.piece = (uint32_t)((g % per_sub) * nu + s);
-        o.thr = thr + 4 * ssub;
+        o.sub = sub;
+        o.piece = (packet0 + src) * nu + s;
+        o.thr = thr + 4 * (uint64_t)sub;
         return o;
     };
-    fused_wave<L, DEG>(v, active, cnt, nu, i0, N, 0xffffffffu, 0, wlo, wd, s_rows, s_qlane, s_qk,
-                       origin, out, cap, count, n_pieces, n_cand, n_res, n_steps, n_slots);
+    fused_wave<L, DEG>(v, s_top, active, cnt, nu, i0, N, 0xffffffffu, 0, wlo, wd, s_rows, s_qlane,
+                       s_qk, origin, out, cap, count, n_pieces, n_cand, n_res, n_steps, n_slots);
     flush_stats(stats, n_pieces, n_cand, n_res, n_steps, n_slots);
 }
 
-// Work items of uneven size (hr_batch_run).  PERSIST: a fixed grid of waves
-// claims items from *next until the list is exhausted; otherwise workgroup
-// b processes item b.
+// Work items of uneven size (hr_batch_run).  An item lies inside one
+// sub-interval.  PERSIST: a fixed grid of waves claims items from *next
+// until the list is exhausted; otherwise workgroup b processes item b.
 template <int L, int DEG, bool PERSIST>
 __global__ __launch_bounds__(64) void k_items(
     const uint64_t* __restrict__ pool, const hr_item* __restrict__ items, uint32_t n_items,
     unsigned int* __restrict__ next, hr_result* __restrict__ out, uint64_t cap,
     unsigned long long* __restrict__ count, unsigned long long* __restrict__ stats) {
-    constexpr int E = n_entries(DEG);
-    __shared__ uint32_t s_rows[(DEG + 1) * L * 64];
+    __shared__ uint32_t s_rows[DEG * L * 64];
+    __shared__ uint32_t s_top[(DEG + 1) * L];
     __shared__ uint32_t s_qlane[kQueue];
     __shared__ uint32_t s_qk[kQueue];
     const int lane = threadIdx.x;
@@ -548,18 +631,10 @@ __global__ __launch_bounds__(64) void k_items(
         const uint64_t p_end = (uint64_t)I->piece0 + I->npieces;
         const bool active = p_begin < p_end;
         const uint32_t cnt = active ? (uint32_t)hr::umin(nu, p_end - p_begin) : 0;
-        hr::Word<L> v[E];
-        if (active) {
-            const uint64_t* T = pool + I->table;
-            uint32_t cb[DEG][4];
-            binom_limbs<DEG>(p_begin, cb);
-            static_for<0, DEG + 1>([&](auto J) {
-                row_start<L, DEG, decltype(J)::value>(T, cb, v + entry(DEG, decltype(J)::value, 0));
-            });
-        } else {
-#pragma unroll
-            for (int e = 0; e < E; ++e) hr::wzero(v[e]);
-        }
+        const uint64_t* T = pool + I->table;
+        load_top<L, DEG>(T, s_top);
+        hr::Word<L> v[n_low(DEG)];
+        start_low<L, DEG>(T, p_begin, active, v);
         auto origin = [&](uint32_t src, uint32_t s) {
             Origin o;
             o.job = I->job;
@@ -568,9 +643,9 @@ __global__ __launch_bounds__(64) void k_items(
             o.thr = I->thr;
             return o;
         };
-        fused_wave<L, DEG>(v, active, cnt, nu, p_begin, I->N, I->last_piece, I->last_N, I->win_lo,
-                           I->win_d, s_rows, s_qlane, s_qk, origin, out, cap, count, n_pieces,
-                           n_cand, n_res, n_steps, n_slots);
+        fused_wave<L, DEG>(v, s_top, active, cnt, nu, p_begin, I->N, I->last_piece, I->last_N,
+                           I->win_lo, I->win_d, s_rows, s_qlane, s_qk, origin, out, cap, count,
+                           n_pieces, n_cand, n_res, n_steps, n_slots);
         if (PERSIST) {
             uint32_t c = 0;
             if (lane == 0) c = atomicAdd(next, 1u);
@@ -852,12 +927,13 @@ hr_status hr_pipeline(hr_ctx* ctx, const uint64_t* table, uint32_t n_sub, uint32
     if (hipSetDevice(ctx->device) != hipSuccess) return HR_EDEVICE;
     hipStream_t st = as_stream(stream);
     const uint32_t nu = pick_nu(n_sub, tau);
-    const uint64_t lanes = (uint64_t)n_sub * ((tau + nu - 1) / nu);
-    const uint64_t blocks = (lanes + 63) / 64;
+    const uint32_t per_sub = (tau + nu - 1) / nu;
+    const uint32_t wps = (per_sub + 63) / 64;       // waves per sub-interval
+    const uint64_t blocks = (uint64_t)n_sub * wps;
     if (blocks > 0xffffffffull) return HR_EINVAL;
     HR_DISPATCH(width_bits, degree,
                 (k_pipeline<L_, D_><<<dim3((uint32_t)blocks), dim3(64), 0, st>>>(
-                    table, n_sub, tau, nu, N, win, thr, out, cap,
+                    table, n_sub, tau, nu, wps, N, win, thr, out, cap,
                     (unsigned long long*)count, stat_slots(ctx, stats))));
     const hr_status s = launched();
     return s != HR_OK ? s : flush_stat_slots(ctx, stats, st);
