@@ -398,6 +398,77 @@ __device__ __forceinline__ void load_top(const uint64_t* __restrict__ T, uint32_
     __syncthreads();
 }
 
+// Top 64 bits of P_i(k) = sum_j r_j C(k, j) mod 1, exactly, for the piece
+// whose rows lane src published (r_0..r_(DEG-1) in s_rows, r_DEG = s_top
+// row DEG); C(k, j) is built up one j at a time.
+template <int L, int DEG>
+__device__ __forceinline__ uint64_t piece_value(const uint32_t* s_rows, const uint32_t* s_top,
+                                                uint32_t src, uint64_t k) {
+    hr::Word<L> V;
+#pragma unroll
+    for (int w = 0; w < L; ++w) V.w[w] = s_rows[w * 64 + src];
+    unsigned __int128 ck = 1;
+    static_for<1, DEG + 1>([&](auto J) {
+        constexpr int j = decltype(J)::value;
+        ck = hr::binom_step(ck, k, j);
+        hr::Word<L> r;
+        if constexpr (j < DEG) {
+#pragma unroll
+            for (int w = 0; w < L; ++w) r.w[w] = s_rows[(j * L + w) * 64 + src];
+        } else {
+            lds_word<L>(s_top + DEG * L, r);
+        }
+        uint32_t m[4];
+        hr::split128(ck, m);
+        hr::wmac128(V, r, m);
+    });
+    return top64(V);
+}
+
+// Cheap exact rejection of a candidate.  With R_j the top 128 bits of r_j,
+// V' = sum_j R_j C(k, j) mod 2^128 undershoots the top 128 bits of P_i(k) by
+// E in [0, sum_j C(k, j)) units of 2^-128 (each dropped low part is below
+// one unit), so the exact top 64 bits t lie in [t', t' + M] with
+// t' = V' div 2^64 and M = DEG + 2 + sum_j (C(k, j) div 2^64).  When that
+// whole range is inside the reject interval [thr[2], thr[3]] and misses the
+// HR interval [thr[0], thr[1]], classify() would return 0 for t: true is
+// returned and the full-width evaluation is skipped.  Always false for
+// W = 128, where nothing is dropped and the evaluation is as cheap.
+template <int L, int DEG>
+__device__ __forceinline__ bool top_rejects(const uint32_t* s_rows, const uint32_t* s_top,
+                                            uint32_t src, uint64_t k,
+                                            const uint64_t* __restrict__ thr) {
+    if constexpr (L <= 4) {
+        return false;
+    } else {
+        hr::Word<4> V;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) V.w[w] = s_rows[(L - 4 + w) * 64 + src];
+        unsigned __int128 ck = 1;
+        uint64_t M = DEG + 2;
+        static_for<1, DEG + 1>([&](auto J) {
+            constexpr int j = decltype(J)::value;
+            ck = hr::binom_step(ck, k, j);
+            M += (uint64_t)(ck >> 64);
+            hr::Word<4> r;
+            if constexpr (j < DEG) {
+#pragma unroll
+                for (int w = 0; w < 4; ++w) r.w[w] = s_rows[(j * L + L - 4 + w) * 64 + src];
+            } else {
+                lds_word<4>(s_top + DEG * L + L - 4, r);
+            }
+            uint32_t m[4];
+            hr::split128(ck, m);
+            hr::wmac128(V, r, m);
+        });
+        const uint64_t t = top64(V);
+        const uint64_t hr_lo = thr[0], hr_hi = thr[1], rej_lo = thr[2], rej_hi = thr[3];
+        const bool in_rej = t >= rej_lo && rej_hi >= M && t <= rej_hi - M;
+        const bool off_hr = t > hr_hi || t + M < hr_lo;   // t + M < 2^64 here (t <= rej_hi - M)
+        return in_rej && off_hr;
+    }
+}
+
 // The per-wave body of the fused pass.  Each lane owns a packet of up to nu
 // consecutive pieces (cnt of them live, starting at piece p_begin) of the
 // wave's sub-interval and keeps the low entries of its difference table in
@@ -467,28 +538,13 @@ __device__ __forceinline__ void fused_wave(
             for (uint32_t e = lane; e < qn; e += 64) {   // drain
                 const uint32_t src = s_qlane[e];
                 const uint64_t k = s_qk[e];
-                // P_i(k) = sum_j r_j C(k, j); C(k, j) built up one j at a time
-                hr::Word<L> V;
-#pragma unroll
-                for (int w = 0; w < L; ++w) V.w[w] = s_rows[w * 64 + src];
-                unsigned __int128 ck = 1;
-                static_for<1, DEG + 1>([&](auto J) {
-                    constexpr int j = decltype(J)::value;
-                    ck = hr::binom_step(ck, k, j);
-                    hr::Word<L> r;
-                    if constexpr (j < DEG) {
-#pragma unroll
-                        for (int w = 0; w < L; ++w) r.w[w] = s_rows[(j * L + w) * 64 + src];
-                    } else {
-                        lds_word<L>(s_top + DEG * L, r);
-                    }
-                    uint32_t m[4];
-                    hr::split128(ck, m);
-                    hr::wmac128(V, r, m);
-                });
-                const uint64_t t = top64(V);
                 const Origin o = origin(src, s);
-                const uint8_t cls = classify<L>(t, o.thr);
+                uint8_t cls = 0;
+                uint64_t t = 0;
+                if (!top_rejects<L, DEG>(s_rows, s_top, src, k, o.thr)) {
+                    t = piece_value<L, DEG>(s_rows, s_top, src, k);
+                    cls = classify<L>(t, o.thr);
+                }
                 if (cls) {
                     const unsigned long long pos = atomicAdd(count, 1ull);
                     if (pos < cap) {
