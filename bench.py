@@ -56,18 +56,24 @@ def parse():
     return p.parse_args()
 
 
-def ops_model(spec, pieces, cand, quotients):
+def ops_model(spec, pieces, cand, quotients, full):
     """Algorithmic int32 VALU operations of one pass:
     tabulation: one 32-bit limb add per limb of each difference-row update,
     sum_j (delta - j) W/32 per piece; search: 96 ops per partial quotient of
     the exact closest-point walk plus 12 per candidate step; recheck: each
-    candidate multiplies delta words by a 128-bit binomial (W/32 x 4 limb
-    products truncated to W bits, 2 ops each) and adds them."""
+    candidate multiplies delta words of the top 128 bits of its rows by a
+    128-bit binomial (4 x 4 limb products truncated to 128 bits, 2 ops each)
+    and adds them; the `full` candidates not rejected that way repeat it at
+    the full W bits."""
     L = spec.W // 32
+
+    def rechk(limbs):
+        mul = 2 * sum(max(limbs - j, 0) for j in range(4))
+        return spec.delta * (mul + limbs) + 12
+
     tab = sum(spec.delta - j for j in range(spec.delta + 1)) * L
-    mul = 2 * sum(max(L - j, 0) for j in range(4))
-    rechk = spec.delta * (mul + L) + 12
-    return pieces * tab + quotients * 96 + cand * rechk
+    top = rechk(4) if L > 4 else 0
+    return pieces * tab + quotients * 96 + cand * top + full * rechk(L)
 
 
 def main():
@@ -137,7 +143,7 @@ def main():
     n_res = int(count_h.numpy()[0])
     assert n_res <= cap
     st = stats.cpu().numpy()
-    pieces, cand, quot = int(st[0]), int(st[1]), int(st[3])
+    pieces, cand, quot, full = int(st[0]), int(st[1]), int(st[3]), int(st[5])
     res = res_h[: n_res * _lib.RESULT_BYTES].numpy().view(api.RESULT_DTYPE)
     hr_cases = int((res["cls"] == 1).sum())
     undecided = int((res["cls"] == 2).sum())
@@ -145,7 +151,7 @@ def main():
     args_total = spec.count
     value = args_total / (ms_per_step / 1000)
     kern_avg = sum(kern_ms) / len(kern_ms)
-    ops = ops_model(spec, pieces, cand, quot)
+    ops = ops_model(spec, pieces, cand, quot, full)
     achieved = ops / (kern_avg / 1000) / 1e12
     line = {
         "metric": METRIC,
@@ -167,6 +173,7 @@ def main():
                      "frac": achieved / (PEAK_INT32_OPS / 1e12), "traffic": None,
                      "kernel": "k_pipeline<8,4>", "kernel_ms": kern_avg},
         "hr_cases": hr_cases, "undecided": undecided, "candidates": cand,
+        "full_width_evaluations": full,
         "partial_quotients": quot, "quotients_per_piece": quot / max(pieces, 1),
         "nmdm_wave64": 1.0 - quot / int(st[4]) if int(st[4]) else 0.0,
         "host_prep_s": prep_s,

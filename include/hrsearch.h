@@ -197,7 +197,8 @@ typedef struct {
  * quotients, [4] wave slots spent in the closest-point walk (sum over waves
  * and pieces of the slowest lane's partial quotients times the live lanes;
  * 1 - [3]/[4] is the loop divergence NMDM of the paper's Sec. 2.2);
- * [5..7] reserved.
+ * [5] candidates evaluated at full width (the others were rejected exactly
+ * from the top 128 bits of their piece's rows); [6..7] reserved.
  * Errors: as hr_tabulate / hr_recheck, N == 0, or N^degree >= 2^128.
  */
 hr_status hr_pipeline(hr_ctx* ctx, const uint64_t* table, uint32_t n_sub, uint32_t degree,

@@ -211,7 +211,7 @@ class Runner:
     def stats_dict(self):
         st = self.stats.cpu().numpy()
         return {"pieces": int(st[0]), "candidates": int(st[1]), "results": int(st[2]),
-                "partial_quotients": int(st[3]),
+                "partial_quotients": int(st[3]), "full_evaluations": int(st[5]),
                 "nmdm": 1.0 - int(st[3]) / int(st[4]) if int(st[4]) else 0.0}
 
 

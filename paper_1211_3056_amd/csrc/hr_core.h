@@ -224,17 +224,13 @@ HR_HD void closest_left(uint64_t a, uint64_t b, uint32_t n, Near& r) {
 
 // Next point to the left of point x among the n points (three-distance
 // theorem: the gap left of a point is alpha, beta or alpha + beta).
+// Selects, not branches: lanes of a wave take different cases.
 HR_HD void pred(const Near& r, uint32_t n, uint32_t& x, uint64_t& gap) {
-    if (x >= r.u) {
-        x -= r.u;
-        gap = r.alpha;
-    } else if ((uint64_t)x + r.v < n) {
-        x += r.v;
-        gap = r.beta;
-    } else {
-        x = x - r.u + r.v;
-        gap = r.alpha + r.beta;
-    }
+    const bool right = x >= r.u;                    // x - u exists
+    const bool left = (uint64_t)x + r.v < n;        // x + v exists
+    const uint32_t down = x - r.u;                  // wraps when !right; unused then
+    x = right ? down : (left ? x + r.v : down + r.v);
+    gap = right ? r.alpha : (left ? r.beta : r.alpha + r.beta);
 }
 
 // Resumable enumeration of the hits of one instance: every k < n with
@@ -260,6 +256,13 @@ HR_HD void iter_init(HitIter& it, uint64_t a, uint64_t b, uint32_t n, uint64_t D
                      uint32_t* steps = nullptr) {
     it.n = n;
     it.D = D;
+    // defined state for every field: iter_next reads them all, also when done
+    it.r = Near{0, 1, 1, 0, 0, 0, 0};
+    it.P = 1;
+    it.x = 0;
+    it.k = 0;
+    it.dist = 0;
+    it.visited = 1;
     it.done = (n == 0 || D == 0);
     if (steps) *steps = 0;
     if (it.done) return;
@@ -281,28 +284,23 @@ HR_HD void iter_init(HitIter& it, uint64_t a, uint64_t b, uint32_t n, uint64_t D
     it.visited = 1;
 }
 
-// Next hit into k; false when there is none left.
+// Next hit into k; false when there is none left.  Written with selects:
+// the lanes of a wave are at different points of their walks.
 HR_HD bool iter_next(HitIter& it, uint64_t& k) {
-    if (it.done) return false;
+    const bool has = !it.done;
     k = it.k;
-    if (it.P < it.n - it.k) {
-        it.k += it.P;
-    } else {                     // all repeats of x reported: go left
-        if (it.visited == it.P) {
-            it.done = true;
-        } else {
-            uint64_t gap;
-            pred(it.r, it.P, it.x, gap);
-            if (gap >= it.D - it.dist) {
-                it.done = true;
-            } else {
-                it.dist += gap;
-                it.k = it.x;
-                ++it.visited;
-            }
-        }
-    }
-    return true;
+    const bool repeat = it.P < it.n - it.k;     // another repeat of x follows
+    uint32_t x = it.x;
+    uint64_t gap;
+    pred(it.r, it.P, x, gap);                   // otherwise go left
+    const bool stop = it.visited == it.P || gap >= it.D - it.dist;
+    const bool left = has && !repeat && !stop;
+    it.done = it.done || (has && !repeat && stop);
+    it.k = (has && repeat) ? it.k + it.P : (left ? x : it.k);
+    it.x = left ? x : it.x;
+    it.dist = left ? it.dist + gap : it.dist;
+    it.visited += left ? 1u : 0u;
+    return has;
 }
 
 // Calls emit(k) for every hit, in the order above; returns their number.

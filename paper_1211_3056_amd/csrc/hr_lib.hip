@@ -485,7 +485,8 @@ __device__ __forceinline__ void fused_wave(
     uint64_t p_begin, uint32_t N, uint32_t last_piece, uint32_t last_N, uint64_t wlo, uint64_t wd,
     uint32_t* s_rows, uint32_t* s_qlane, uint32_t* s_qk, OriginFn&& origin,
     hr_result* __restrict__ out, uint64_t cap, unsigned long long* __restrict__ count,
-    uint64_t& n_pieces, uint64_t& n_cand, uint64_t& n_res, uint64_t& n_steps, uint64_t& n_slots) {
+    uint64_t& n_pieces, uint64_t& n_cand, uint64_t& n_res, uint64_t& n_steps, uint64_t& n_slots,
+    uint64_t& n_full) {
     const int lane = threadIdx.x;
     for (uint32_t s = 0; s < nu; ++s) {
         const bool live = active && s < cnt;
@@ -542,6 +543,7 @@ __device__ __forceinline__ void fused_wave(
                 uint8_t cls = 0;
                 uint64_t t = 0;
                 if (!top_rejects<L, DEG>(s_rows, s_top, src, k, o.thr)) {
+                    ++n_full;
                     t = piece_value<L, DEG>(s_rows, s_top, src, k);
                     cls = classify<L>(t, o.thr);
                 }
@@ -599,7 +601,7 @@ constexpr int kStatFields = 8;
 
 __device__ __forceinline__ void flush_stats(unsigned long long* slots, uint64_t n_pieces,
                                             uint64_t n_cand, uint64_t n_res, uint64_t n_steps,
-                                            uint64_t n_slots) {
+                                            uint64_t n_slots, uint64_t n_full) {
     if (!slots) return;
     unsigned long long* stats = slots + (blockIdx.x % kStatSlots) * kStatFields;
     n_pieces = wave_sum(n_pieces);
@@ -607,12 +609,14 @@ __device__ __forceinline__ void flush_stats(unsigned long long* slots, uint64_t 
     n_res = wave_sum(n_res);
     n_steps = wave_sum(n_steps);
     n_slots = wave_sum(n_slots);
+    n_full = wave_sum(n_full);
     if (threadIdx.x == 0) {
         atomicAdd(stats + 0, (unsigned long long)n_pieces);
         atomicAdd(stats + 1, (unsigned long long)n_cand);
         atomicAdd(stats + 2, (unsigned long long)n_res);
         atomicAdd(stats + 3, (unsigned long long)n_steps);
         atomicAdd(stats + 4, (unsigned long long)n_slots);
+        atomicAdd(stats + 5, (unsigned long long)n_full);
     }
 }
 
@@ -644,7 +648,7 @@ __global__ __launch_bounds__(64) void k_pipeline(
     start_low<L, DEG>(T, i0, active, v);
     const uint64_t wlo = win[2 * (uint64_t)sub];
     const uint64_t wd = win[2 * (uint64_t)sub + 1];
-    uint64_t n_pieces = 0, n_cand = 0, n_res = 0, n_steps = 0, n_slots = 0;
+    uint64_t n_pieces = 0, n_cand = 0, n_res = 0, n_steps = 0, n_slots = 0, n_full = 0;
     auto origin = [&](uint32_t src, uint32_t s) {
         Origin o;
         o.job = 0;
@@ -654,8 +658,9 @@ __global__ __launch_bounds__(64) void k_pipeline(
         return o;
     };
     fused_wave<L, DEG>(v, s_top, active, cnt, nu, i0, N, 0xffffffffu, 0, wlo, wd, s_rows, s_qlane,
-                       s_qk, origin, out, cap, count, n_pieces, n_cand, n_res, n_steps, n_slots);
-    flush_stats(stats, n_pieces, n_cand, n_res, n_steps, n_slots);
+                       s_qk, origin, out, cap, count, n_pieces, n_cand, n_res, n_steps, n_slots,
+                       n_full);
+    flush_stats(stats, n_pieces, n_cand, n_res, n_steps, n_slots, n_full);
 }
 
 // Work items of uneven size (hr_batch_run).  An item lies inside one
@@ -671,7 +676,7 @@ __global__ __launch_bounds__(64) void k_items(
     __shared__ uint32_t s_qlane[kQueue];
     __shared__ uint32_t s_qk[kQueue];
     const int lane = threadIdx.x;
-    uint64_t n_pieces = 0, n_cand = 0, n_res = 0, n_steps = 0, n_slots = 0;
+    uint64_t n_pieces = 0, n_cand = 0, n_res = 0, n_steps = 0, n_slots = 0, n_full = 0;
     uint32_t idx;
     if (PERSIST) {
         uint32_t c = 0;
@@ -701,7 +706,7 @@ __global__ __launch_bounds__(64) void k_items(
         };
         fused_wave<L, DEG>(v, s_top, active, cnt, nu, p_begin, I->N, I->last_piece, I->last_N,
                            I->win_lo, I->win_d, s_rows, s_qlane, s_qk, origin, out, cap, count,
-                           n_pieces, n_cand, n_res, n_steps, n_slots);
+                           n_pieces, n_cand, n_res, n_steps, n_slots, n_full);
         if (PERSIST) {
             uint32_t c = 0;
             if (lane == 0) c = atomicAdd(next, 1u);
@@ -710,7 +715,7 @@ __global__ __launch_bounds__(64) void k_items(
             idx = n_items;
         }
     }
-    flush_stats(stats, n_pieces, n_cand, n_res, n_steps, n_slots);
+    flush_stats(stats, n_pieces, n_cand, n_res, n_steps, n_slots, n_full);
 }
 
 __global__ void k_zero_u32(unsigned int* p) { *p = 0u; }
