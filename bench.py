@@ -26,6 +26,23 @@ METRIC = "binary64 args checked/sec (exp, 2^40 slice); batched vs plain speedup,
 PEAK_INT32_OPS = 256 * 64 * 2.4e9     # 256 CUs x 64 lanes x 2.4 GHz, one op/lane/clock
 PEAK_HBM = 8.0e12                     # bytes/s
 
+# HBM bytes per launch measured by rocprofv3 (FETCH_SIZE x 1.997 and
+# WRITE_SIZE x 0.999, the factors a 1 GiB copy gives; summary under
+# profiles/), valid only for the kernel sources they were taken on.
+PROFILED_SOURCES = "f7212bb512e0d6b7"      # sha256 prefix of hr_lib.hip + hr_core.h
+PROFILED_TRAFFIC = {"k_pipeline<8,4>": 4.96e6, "k_tabulate<8,4>": 68.86e6}
+
+
+def profiled_traffic(kernel):
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1211_3056_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ("hr_lib.hip", "hr_core.h"):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return PROFILED_TRAFFIC.get(kernel) if h.hexdigest()[:16] == PROFILED_SOURCES else None
+
+
 # The paper's own figures (Sec. 6, Tables 5-6): whole computation (tabulation
 # + search) of exp on binary64 [1, 2), Fermi C2070 + Xeon X5650 against the
 # same Xeon: context, not a target.
@@ -170,7 +187,8 @@ def main():
                    "form": "fused", "sub_intervals": n_sub, "pieces": pieces},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_INT32_OPS / 1e12,
                      "unit": "Tops/s (int32 VALU, algorithmic)",
-                     "frac": achieved / (PEAK_INT32_OPS / 1e12), "traffic": None,
+                     "frac": achieved / (PEAK_INT32_OPS / 1e12),
+                     "traffic": profiled_traffic("k_pipeline<8,4>"),
                      "kernel": "k_pipeline<8,4>", "kernel_ms": kern_avg},
         "hr_cases": hr_cases, "undecided": undecided, "candidates": cand,
         "full_width_evaluations": full,
@@ -236,8 +254,9 @@ def bench_tabulation(spec, table, ctx, stream, steps):
     torch.cuda.synchronize()
     ms = sum(a.elapsed_time(b) for a, b in evs) / steps
     nbytes = table.numel() * 8 + pieces * 16
-    return {"kernel": f"k_tabulate<{spec.W // 32},{spec.delta}>", "kernel_ms": ms,
-            "pieces": pieces, "bytes": nbytes, "hbm_GBps": nbytes / (ms / 1000) / 1e9,
+    kernel = f"k_tabulate<{spec.W // 32},{spec.delta}>"
+    return {"kernel": kernel, "kernel_ms": ms, "pieces": pieces, "bytes": nbytes,
+            "traffic": profiled_traffic(kernel), "hbm_GBps": nbytes / (ms / 1000) / 1e9,
             "hbm_frac": nbytes / (ms / 1000) / PEAK_HBM,
             "pieces_per_s": pieces / (ms / 1000)}
 
