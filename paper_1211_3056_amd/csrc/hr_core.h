@@ -53,26 +53,23 @@ HR_HD Recip recip(uint64_t den) {
 
 // min(floor(num / den), cap) for den > 0, cap < 2^32, and the remainder
 // num - q den when q < cap (unspecified when q = cap).
-// The binary64 estimate of the quotient of the (rounded) operands is within
-// 2^-10 of the true quotient whenever it is below cap + 2, so its floor is
-// off by at most one; one exact multiply-compare corrects it and yields the
-// remainder.  Larger quotients saturate at cap: callers only need to know
-// that they reach cap.
+// The binary64 estimate e of the quotient of the (rounded) operands is
+// within 2^-10 of the true quotient q + f (0 <= f < 1) whenever it is below
+// cap + 2.  Lowered by 2^-9, its floor is therefore q or q - 1, never q + 1:
+// k den <= num fits in 64 bits, and one compare of the remainder with den
+// (plus one subtraction) finishes the division.  Larger quotients saturate
+// at cap: callers only need to know that they reach cap.
 HR_HD uint32_t quot_rem(uint64_t num, const Recip& R, uint32_t cap, uint64_t& rem) {
     const uint64_t den = R.den;
     const double e = u64_to_f64(num) * R.r;
     const bool big = e > (double)cap + 2.0;
-    const uint32_t k = (uint32_t)__builtin_fmin(e, 4294967295.0);
-    // k * den as a 96-bit product: lo (64 bits) and whether bits >= 64 are set
-    const uint64_t t1 = (uint64_t)k * (uint32_t)den;
-    const uint64_t t2 = (uint64_t)k * (uint32_t)(den >> 32) + (t1 >> 32);
-    const uint64_t lo = (t2 << 32) | (uint32_t)t1;
-    const bool over = (t2 >> 32) != 0 || lo > num;
-    const uint64_t r0 = num - lo;
-    const bool under = !over && r0 >= den;
-    // r0 + den when over, r0 - den when under (masks, not branches)
-    rem = r0 + (den & (0 - (uint64_t)over)) - (den & (0 - (uint64_t)under));
-    const uint64_t kk = (uint64_t)k - over + under;
+    const uint32_t k = (uint32_t)__builtin_fmin(__builtin_fmax(e - 0x1p-9, 0.0), 4294967295.0);
+    const uint64_t kd = (uint64_t)k * (uint32_t)den +
+                        ((uint64_t)(k * (uint32_t)(den >> 32)) << 32);   // k den, exact
+    const uint64_t r0 = num - kd;      // in [0, 2 den)
+    const bool under = r0 >= den;      // k = q - 1
+    rem = under ? r0 - den : r0;
+    const uint64_t kk = (uint64_t)k + under;
     return (big || kk >= cap) ? cap : (uint32_t)kk;
 }
 
