@@ -56,7 +56,7 @@ PAPER_CONTEXT = {
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-plain", action="store_true")
@@ -189,7 +189,8 @@ def main():
                      "unit": "Tops/s (int32 VALU, algorithmic)",
                      "frac": achieved / (PEAK_INT32_OPS / 1e12),
                      "traffic": profiled_traffic("k_pipeline<8,4>"),
-                     "kernel": "k_pipeline<8,4>", "kernel_ms": kern_avg},
+                     "kernel": "k_pipeline<8,4>", "kernel_ms": kern_avg,
+                     "kernel_ms_median": sorted(kern_ms)[len(kern_ms) // 2]},
         "hr_cases": hr_cases, "undecided": undecided, "candidates": cand,
         "full_width_evaluations": full,
         "partial_quotients": quot, "quotients_per_piece": quot / max(pieces, 1),
@@ -223,11 +224,30 @@ def main():
         t0 = time.perf_counter()
         ohr.pipeline(job, subs=subs)
         cpu_s = time.perf_counter() - t0
+        one = subs[: max(1, len(subs) // 8)]           # a smaller sample on one thread
+        t0 = time.perf_counter()
+        ohr.pipeline(job, subs=one, threads=1)
+        one_s = time.perf_counter() - t0
         line["cpu_baseline"] = {"value": len(subs) * spec.per_sub / cpu_s, "unit": "args/s",
                                 "cores": native.threads_default(), "kind": "oracle",
                                 "sample": f"{len(subs)} of {n_sub} sub-intervals "
-                                          f"({len(subs) * spec.per_sub} args), {cpu_s:.1f} s"}
+                                          f"({len(subs) * spec.per_sub} args), {cpu_s:.1f} s",
+                                "value_1_thread": len(one) * spec.per_sub / one_s,
+                                "sample_1_thread": f"{len(one)} sub-intervals, {one_s:.1f} s",
+                                "nproc": os.cpu_count(), "cpu_model": cpu_model(),
+                                "gpu_over_cpu": value / (len(subs) * spec.per_sub / cpu_s)}
     print(json.dumps(line))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def bench_tabulation(spec, table, ctx, stream, steps):
@@ -384,7 +404,8 @@ def bench_serve(args, pool):
                  "capacity_jobs_per_s": capacity, "arrival_rate_jobs_per_s": rate,
                  "device_steps": be.steps - steps0, "prep_workers": args.prep_workers,
                  "hbm_budget_bytes": srv.budget, "peak_hbm_bytes": srv.peak_used,
-                 "same_hr_as_saturated_run": all(a.hr == b.hr for a, b in zip(sat, states))})
+                 "same_hr_as_saturated_run": all(np.array_equal(a.hr, b.hr)
+                                                 for a, b in zip(sat, states))})
     return summ
 
 

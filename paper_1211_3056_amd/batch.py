@@ -24,7 +24,7 @@ import numpy as np
 import torch
 
 from . import _lib, api, autotune
-from .plan import BatchJob, PlannedJob, PlannedSub, plan_job  # noqa: F401
+from .plan import BatchJob, PlannedJob, PlannedSub, plan_job, split_by_job  # noqa: F401
 from .prep import JobSpec, SubPreparer, is_hr
 
 M64 = 1 << 64
@@ -236,9 +236,9 @@ def finish(plan: Plan, results: np.ndarray):
     """Per-job sorted HR offsets (argument X0 + m h), undecided values
     decided at high precision on the host."""
     out = {}
-    for pj in plan.jobs:
+    per_job = split_by_job(results, [pj.job.job_id for pj in plan.jobs])
+    for pj, res in zip(plan.jobs, per_job):
         jid = pj.job.job_id
-        res = results[results["job"] == jid]
         starts = np.array([sp.start for sp in pj.subs], dtype=np.int64)
         Ns = np.array([sp.N for sp in pj.subs], dtype=np.int64)
         sub = res["sub"].astype(np.int64)

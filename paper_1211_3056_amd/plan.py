@@ -75,3 +75,37 @@ def plan_job(job: BatchJob) -> PlannedJob:
         if s.pieces ** delta >= 1 << 128 or s.N ** delta >= 1 << 128:
             raise ValueError("piece count or length too large for the degree")
     return PlannedJob(job, delta, W, uf, subs)
+
+
+def split_by_job(res: np.ndarray, job_ids):
+    """Result records of each job, in job_ids order; within a job the records
+    keep their device order (see canonical()).  One stable 16-bit radix sort
+    of the step's records by local job index, then contiguous slices."""
+    ids = np.asarray(job_ids, dtype=np.int64)
+    if ids.size == 0:
+        return []
+    if ids.size >= 1 << 16:
+        raise ValueError("too many jobs in one step")
+    job = res["job"].astype(np.int64)
+    other = ids.size                                   # bucket of unknown job ids
+    if ids.max() < 1 << 24:
+        lut = np.full(int(ids.max()) + 2, other, dtype=np.int64)
+        lut[ids] = np.arange(ids.size)
+        local = lut[np.minimum(job, ids.max() + 1)]
+    else:
+        srt = np.argsort(ids)
+        pos = np.minimum(np.searchsorted(ids[srt], job), ids.size - 1)
+        local = np.where(ids[srt][pos] == job, srt[pos], other)
+    local = local.astype(np.uint16)
+    order = np.argsort(local, kind="stable")
+    bounds = np.concatenate([[0], np.cumsum(np.bincount(local, minlength=other + 1))])
+    # gather whole 32-byte records as rows of 4 uint64 (a structured gather is
+    # several times slower)
+    rows = np.take(np.ascontiguousarray(res).view(np.uint64).reshape(-1, 4), order, axis=0)
+    res = rows.reshape(-1).view(RESULT_DTYPE)
+    return [res[bounds[i]:bounds[i + 1]] for i in range(ids.size)]
+
+
+def canonical(records: np.ndarray) -> np.ndarray:
+    """Records sorted by (job, sub, piece, k): a device-order-free form."""
+    return records[np.lexsort((records["k"], records["piece"], records["sub"], records["job"]))]

@@ -30,7 +30,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import autotune
-from .plan import ITEM_DTYPE, RESULT_DTYPE, BatchJob, plan_job
+from .plan import ITEM_DTYPE, RESULT_DTYPE, BatchJob, plan_job, split_by_job
 from .prep import JobSpec, SubPreparer, is_hr
 
 RESULT_RESERVE = 64 * 32          # bytes reserved per job for its result records
@@ -74,22 +74,22 @@ def prepare_job(job: BatchJob, target_item_ns: float = 2000.0) -> Prepared:
                     np.concatenate(tables), np.array(rows, dtype=ITEM_DTYPE), time.time() - t0)
 
 
-def decide_results(prep: Prepared, res: np.ndarray):
-    """Sorted HR offsets of one job from its result records."""
+def decide_results(prep: Prepared, res: np.ndarray) -> np.ndarray:
+    """Sorted HR offsets (int64 array) of one job from its result records."""
     from mpmath import mpf
     if len(res) == 0:
-        return []
+        return np.zeros(0, np.int64)
     starts = np.array([s[0] for s in prep.subs], dtype=np.int64)
     Ns = np.array([s[2] for s in prep.subs], dtype=np.int64)
     sub = res["sub"].astype(np.int64)
     m = starts[sub] + res["piece"].astype(np.int64) * Ns[sub] + res["k"].astype(np.int64)
-    out = m[res["cls"] == 1].tolist()
+    sure = m[res["cls"] == 1]
     und = m[res["cls"] == 2].tolist()
     if und:
         spec = JobSpec(prep.job.fname, prep.job.X0, prep.job.count, prep.job.s, prep.job.mode)
         uf = mpf(prep.uf)
-        out += [x for x in und if is_hr(spec, x, uf)]
-    return sorted(out)
+        sure = np.concatenate([sure, np.array([x for x in und if is_hr(spec, x, uf)], np.int64)])
+    return np.sort(sure)
 
 
 @dataclass
@@ -101,8 +101,8 @@ class JobState:
     t_ready: float = 0.0
     t_admit: float = 0.0
     t_done: float = 0.0
-    hr: list = field(default_factory=list)
-    records: np.ndarray | None = None
+    hr: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int64))   # sorted offsets
+    records: np.ndarray | None = None   # result records, device order (plan.canonical sorts)
     error: str = ""
     dev: object = None            # device handle of the admitted job (backend-specific)
 
@@ -168,8 +168,7 @@ class GpuBackend:
             self.out = torch.empty(self.cap * _lib.RESULT_BYTES, dtype=torch.uint8, device="cuda")
         res = self.out[: n * _lib.RESULT_BYTES].cpu().numpy().view(RESULT_DTYPE)
         self.steps += 1
-        return [np.sort(res[res["job"] == s.job.job_id], order=["sub", "piece", "k"])
-                for s in states]
+        return split_by_job(res, [s.job.job_id for s in states])
 
 
 def make_pool(workers: int):

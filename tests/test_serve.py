@@ -120,3 +120,18 @@ def test_prepared_jobs_skip_the_pool(pool):
     states = srv.serve(jobs, np.zeros(5), realtime=False, prepared=preps)
     assert all(s.status == "done" for s in states)
     assert srv.blocked_admissions >= 4 and be.max_resident == 1
+
+
+def test_split_by_job_equals_filter():
+    from paper_1211_3056_amd.plan import RESULT_DTYPE, canonical, split_by_job
+    rng = np.random.default_rng(3)
+    r = np.zeros(5000, dtype=RESULT_DTYPE)
+    for f, hi in (("job", 7), ("sub", 4), ("piece", 50), ("k", 1000), ("cls", 3)):
+        r[f] = rng.integers(0, hi, r.size)
+    for ids in ([3, 0, 9, 6], [1 << 30, 2, 5]):
+        if ids[0] == 1 << 30:
+            r["job"][:100] = 1 << 30
+        for jid, got in zip(ids, split_by_job(r, ids)):
+            want = r[r["job"] == jid]
+            assert got.tobytes() == want.tobytes()          # device order kept
+            assert canonical(got).tobytes() == canonical(want).tobytes()
