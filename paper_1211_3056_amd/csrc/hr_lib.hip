@@ -523,17 +523,24 @@ __device__ __forceinline__ void fused_wave(
         }
         for (;;) {
             uint32_t qn = 0;
-            for (;;) {   // fill: one hit per lane and round while room remains
-                uint64_t k = 0;
-                const bool has = hr::iter_next(it, k);
-                const uint64_t mask = __ballot(has);
-                if (has) {
-                    const uint32_t pos = qn + lanes_below(mask);
+            for (;;) {   // fill: two hits per lane and round while room remains
+                uint64_t k1 = 0, k2 = 0;
+                const bool h1 = hr::iter_next(it, k1);
+                const bool h2 = hr::iter_next(it, k2);   // implies h1
+                const uint64_t m1 = __ballot(h1), m2 = __ballot(h2);
+                const uint32_t n1 = (uint32_t)__popcll(m1);
+                if (h1) {
+                    const uint32_t pos = qn + lanes_below(m1);
                     s_qlane[pos] = (uint32_t)lane;
-                    s_qk[pos] = (uint32_t)k;
+                    s_qk[pos] = (uint32_t)k1;
                 }
-                qn += (uint32_t)__popcll(mask);
-                if (mask == 0 || qn + 64 > kQueue) break;
+                if (h2) {
+                    const uint32_t pos = qn + n1 + lanes_below(m2);
+                    s_qlane[pos] = (uint32_t)lane;
+                    s_qk[pos] = (uint32_t)k2;
+                }
+                qn += n1 + (uint32_t)__popcll(m2);
+                if (m2 == 0 || qn + 128 > kQueue) break;
             }
             __syncthreads();
             for (uint32_t e = lane; e < qn; e += 64) {   // drain
