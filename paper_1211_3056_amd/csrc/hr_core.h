@@ -399,6 +399,26 @@ HR_HD unsigned __int128 binom_step(unsigned __int128 c, uint64_t x, int j) {
     return v;
 }
 
+// The same in 64 bits, for x below binom64_limit(J): there j C(x, j) < 2^64
+// for every j <= J, so the product before the exact division fits.
+HR_HD uint64_t binom_step64(uint64_t c, uint64_t x, int j) {
+    const uint64_t inv3 = 0xaaaaaaaaaaaaaaabull, inv5 = 0xcccccccccccccccdull;   // mod 2^64
+    if (j == 1) return x;
+    uint64_t v = c * (x - (uint64_t)(j - 1));
+    if (j == 2) v >>= 1;
+    else if (j == 3) v *= inv3;
+    else if (j == 4) v >>= 2;
+    else if (j == 5) v *= inv5;
+    else if (j == 6) v = (v >> 1) * inv3;
+    return v;
+}
+
+// x(x-1)..(x-J+1) < 2^64 for x < binom64_limit(J), J <= 6.
+HR_HD constexpr uint64_t binom64_limit(int J) {
+    return J <= 2 ? (1ull << 32) : J == 3 ? (1ull << 21) : J == 4 ? (1ull << 16)
+                                 : J == 5 ? (1ull << 12) : (1ull << 10);
+}
+
 // Binomials C(x, 1..J), c[j-1] = C(x, j).
 HR_HD void binoms128(uint64_t x, int J, unsigned __int128* c) {
     unsigned __int128 v = 1;

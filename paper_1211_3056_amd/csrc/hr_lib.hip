@@ -407,6 +407,25 @@ __device__ __forceinline__ uint64_t piece_value(const uint32_t* s_rows, const ui
     hr::Word<L> V;
 #pragma unroll
     for (int w = 0; w < L; ++w) V.w[w] = s_rows[w * 64 + src];
+    // Degrees up to 3 have 64-bit binomials for k < 2^21; when every lane's
+    // do, two-limb multipliers replace the per-lane choice of length.
+    if (DEG <= 3 && __ballot(k >= hr::binom64_limit(DEG)) == 0) {
+        uint64_t c = 1;
+        static_for<1, DEG + 1>([&](auto J) {
+            constexpr int j = decltype(J)::value;
+            c = hr::binom_step64(c, k, j);
+            hr::Word<L> r;
+            if constexpr (j < DEG) {
+#pragma unroll
+                for (int w = 0; w < L; ++w) r.w[w] = s_rows[(j * L + w) * 64 + src];
+            } else {
+                lds_word<L>(s_top + DEG * L, r);
+            }
+            const uint32_t m[2] = {(uint32_t)c, (uint32_t)(c >> 32)};
+            hr::wmac_n<L, 2>(V, r, m);
+        });
+        return top64(V);
+    }
     unsigned __int128 ck = 1;
     static_for<1, DEG + 1>([&](auto J) {
         constexpr int j = decltype(J)::value;

@@ -99,3 +99,54 @@ def test_tabulate_config3_full_size_sampled():
         for i in [0, 1, 511, 1023] + g.integers(0, spec.tau, 4).tolist():
             ra, rb = otab.piece_ab(otab.straightforward_rows(T, 4, int(i), 256), 256)
             assert (int(a[t * spec.tau + i]), int(b[t * spec.tau + i])) == (ra, rb)
+
+
+@pytest.mark.parametrize("W,delta,N", [(256, 4, 1 << 12), (192, 3, 1 << 14), (256, 6, 1 << 10),
+                                       (128, 3, 1 << 14)])
+def test_fused_classes_at_threshold_boundaries(W, delta, N):
+    """Thresholds placed on exact candidate values and up to 8 units either
+    side: the fused pass (rejection from the top 128 bits with its error
+    bound, else full width) must classify every candidate exactly as the
+    plain full-width recheck does, including an HR band that overlaps the
+    reject band."""
+    from paper_1211_3056_amd import api
+    n_sub, tau = 3, 64
+    tabs = synth.random_tables(31 * W + delta, n_sub, delta, W)
+    table = api.to_dev(tabs.reshape(-1), torch.uint64)
+    g = synth.rng(W * 7 + delta)
+    win = np.zeros((n_sub, 2), np.uint64)
+    win[:, 0] = g.integers(0, 2 ** 64, n_sub, dtype=np.uint64, endpoint=False)
+    win[:, 1] = np.uint64((1 << 64) // N * 16)               # ~16 candidates a piece
+    a, b = api.tabulate(table, n_sub, delta, tau, W)
+    Nt = torch.full((n_sub * tau,), N, dtype=torch.uint32, device="cuda")
+    _, _, hits, inst = api.search(a, b, Nt, api.to_dev(win[:, 1], torch.uint64),
+                                  lo=api.to_dev(win[:, 0], torch.uint64), group=tau,
+                                  with_inst=True)
+    dummy = api.to_dev(np.zeros(4 * n_sub, np.uint64), torch.uint64)
+    value, _ = api.recheck(table, n_sub, delta, tau, W, inst, hits, N - 1, dummy)
+    value, inst_h, k_h = value.cpu().numpy(), inst.cpu().numpy(), hits.cpu().numpy()
+    sub_h = inst_h // tau
+    assert value.size > 2000
+    for overlap in (False, True):
+        for off in range(-8, 9):
+            thr = np.zeros((n_sub, 4), np.uint64)
+            for s in range(n_sub):
+                v = np.sort(value[sub_h == s])
+                q = lambda f: int(v[int(f * (v.size - 1))])
+                shift = lambda x, o: np.uint64(min(max(x + o, 0), (1 << 64) - 1))
+                thr[s, 2], thr[s, 3] = shift(q(0.2), off), shift(q(0.7), -off)
+                if overlap:
+                    thr[s, 0], thr[s, 1] = shift(q(0.6), -off), shift(q(0.8), off)
+                else:
+                    thr[s, 0], thr[s, 1] = shift(q(0.75), off), shift(q(0.9), -off)
+            thr_t = api.to_dev(thr.reshape(-1), torch.uint64)
+            _, want_cls = api.recheck(table, n_sub, delta, tau, W, inst, hits, N - 1, thr_t)
+            want_cls = want_cls.cpu().numpy()
+            keep = want_cls != 0
+            want = sorted(zip(sub_h[keep].tolist(), (inst_h[keep] % tau).tolist(),
+                              k_h[keep].tolist(), want_cls[keep].tolist(), value[keep].tolist()))
+            res, _ = api.pipeline(table, n_sub, delta, tau, W, N,
+                                  api.to_dev(win.reshape(-1), torch.uint64), thr_t)
+            got = sorted(zip(res["sub"].tolist(), res["piece"].tolist(), res["k"].tolist(),
+                             res["cls"].tolist(), res["value"].tolist()))
+            assert got == want, (overlap, off)
