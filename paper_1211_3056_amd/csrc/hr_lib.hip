@@ -337,6 +337,15 @@ struct Origin {
     const uint64_t* thr;
 };
 
+// LDS layout of the rows r_0..r_(DEG-1) a lane publishes for the recheck:
+// lane-major, one block of DEG L words per lane, so a lane writes and a
+// reader reads 16-byte vectors.  The block is padded to a multiple of 4
+// words whose quotient by 4 is odd: the 16 lanes of one 128-bit access
+// phase then start on 16 distinct 4-bank groups.
+__host__ __device__ constexpr int row_stride(int L, int deg) {
+    return ((deg * L + 3) / 4) % 2 == 1 ? (deg * L + 3) / 4 * 4 : ((deg * L + 3) / 4 + 1) * 4;
+}
+
 // Register layout of the fused pass.  Row j of the difference table at a
 // piece is the vector Delta^l r_j, l = 0..DEG-j.  Its top entry
 // Delta^(DEG-j) r_j is the leading difference of a polynomial of degree
@@ -406,7 +415,7 @@ __device__ __forceinline__ uint64_t piece_value(const uint32_t* s_rows, const ui
                                                 uint32_t src, uint64_t k) {
     hr::Word<L> V;
 #pragma unroll
-    for (int w = 0; w < L; ++w) V.w[w] = s_rows[w * 64 + src];
+    for (int w = 0; w < L; ++w) V.w[w] = s_rows[src * row_stride(L, DEG) + w];
     // Degrees up to 3 have 64-bit binomials for k < 2^21; when every lane's
     // do, two-limb multipliers replace the per-lane choice of length.
     if (DEG <= 3 && __ballot(k >= hr::binom64_limit(DEG)) == 0) {
@@ -417,7 +426,7 @@ __device__ __forceinline__ uint64_t piece_value(const uint32_t* s_rows, const ui
             hr::Word<L> r;
             if constexpr (j < DEG) {
 #pragma unroll
-                for (int w = 0; w < L; ++w) r.w[w] = s_rows[(j * L + w) * 64 + src];
+                for (int w = 0; w < L; ++w) r.w[w] = s_rows[src * row_stride(L, DEG) + j * L + w];
             } else {
                 lds_word<L>(s_top + DEG * L, r);
             }
@@ -433,7 +442,7 @@ __device__ __forceinline__ uint64_t piece_value(const uint32_t* s_rows, const ui
         hr::Word<L> r;
         if constexpr (j < DEG) {
 #pragma unroll
-            for (int w = 0; w < L; ++w) r.w[w] = s_rows[(j * L + w) * 64 + src];
+            for (int w = 0; w < L; ++w) r.w[w] = s_rows[src * row_stride(L, DEG) + j * L + w];
         } else {
             lds_word<L>(s_top + DEG * L, r);
         }
@@ -462,7 +471,7 @@ __device__ __forceinline__ bool top_rejects(const uint32_t* s_rows, const uint32
     } else {
         hr::Word<4> V;
 #pragma unroll
-        for (int w = 0; w < 4; ++w) V.w[w] = s_rows[(L - 4 + w) * 64 + src];
+        for (int w = 0; w < 4; ++w) V.w[w] = s_rows[src * row_stride(L, DEG) + L - 4 + w];
         unsigned __int128 ck = 1;
         uint64_t M = DEG + 2;
         static_for<1, DEG + 1>([&](auto J) {
@@ -472,7 +481,8 @@ __device__ __forceinline__ bool top_rejects(const uint32_t* s_rows, const uint32
             hr::Word<4> r;
             if constexpr (j < DEG) {
 #pragma unroll
-                for (int w = 0; w < 4; ++w) r.w[w] = s_rows[(j * L + L - 4 + w) * 64 + src];
+                for (int w = 0; w < 4; ++w)
+                    r.w[w] = s_rows[src * row_stride(L, DEG) + j * L + L - 4 + w];
             } else {
                 lds_word<4>(s_top + DEG * L + L - 4, r);
             }
@@ -538,7 +548,7 @@ __device__ __forceinline__ void fused_wave(
             for (int j = 0; j < DEG; ++j)
 #pragma unroll
                 for (int w = 0; w < L; ++w)
-                    s_rows[(j * L + w) * 64 + lane] = v[low_entry(DEG, j, 0)].w[w];
+                    s_rows[lane * row_stride(L, DEG) + j * L + w] = v[low_entry(DEG, j, 0)].w[w];
         }
         for (;;) {
             uint32_t qn = 0;
@@ -656,7 +666,7 @@ __global__ __launch_bounds__(64) void k_pipeline(
     uint32_t N, const uint64_t* __restrict__ win, const uint64_t* __restrict__ thr,
     hr_result* __restrict__ out, uint64_t cap, unsigned long long* __restrict__ count,
     unsigned long long* __restrict__ stats) {
-    __shared__ uint32_t s_rows[DEG * L * 64];   // word-major: [(j L + w) * 64 + lane]
+    __shared__ __align__(16) uint32_t s_rows[64 * row_stride(L, DEG)];   // [lane][j][w], padded rows
     __shared__ uint32_t s_top[(DEG + 1) * L];
     __shared__ uint32_t s_qlane[kQueue];
     __shared__ uint32_t s_qk[kQueue];
@@ -697,7 +707,7 @@ __global__ __launch_bounds__(64) void k_items(
     const uint64_t* __restrict__ pool, const hr_item* __restrict__ items, uint32_t n_items,
     unsigned int* __restrict__ next, hr_result* __restrict__ out, uint64_t cap,
     unsigned long long* __restrict__ count, unsigned long long* __restrict__ stats) {
-    __shared__ uint32_t s_rows[DEG * L * 64];
+    __shared__ __align__(16) uint32_t s_rows[64 * row_stride(L, DEG)];
     __shared__ uint32_t s_top[(DEG + 1) * L];
     __shared__ uint32_t s_qlane[kQueue];
     __shared__ uint32_t s_qk[kQueue];
