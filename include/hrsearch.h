@@ -47,6 +47,7 @@ extern "C" {
 
 #define HR_ABI_VERSION 1
 #define HR_MAX_DEGREE 6
+#define HR_WAVES_FILL 0xffffffffu   /* hr_batch_run: as many waves as stay resident */
 
 typedef struct hr_ctx hr_ctx;
 
@@ -218,11 +219,14 @@ hr_status hr_pipeline(hr_ctx* ctx, const uint64_t* table, uint32_t n_sub, uint32
  *  waves       0: one wave per item (grid = n_items);
  *              > 0: persistent: `waves` one-wave workgroups claim items from
  *              a device counter until none is left (every wave exits when the
- *              list is exhausted)
+ *              list is exhausted); HR_WAVES_FILL: as many waves as the device
+ *              keeps resident for this width and degree (occupancy per CU
+ *              times CUs, queried once), capped at n_items
  *  out, cap, count, stats: as hr_pipeline (results carry the item's job/sub)
  * Piece arguments k must satisfy k^degree < 2^128 and piece indices
  * piece^degree < 2^128 (checked on the host by the caller's planner).
- * Errors: HR_EINVAL for bad width/degree, null pointers, n_items > 2^31.
+ * Errors: HR_EINVAL for bad width/degree, null pointers, n_items > 2^31;
+ * HR_EDEVICE if the occupancy query for HR_WAVES_FILL fails.
  */
 hr_status hr_batch_run(hr_ctx* ctx, const uint64_t* pool, const hr_item* items, uint32_t n_items,
                        uint32_t width_bits, uint32_t degree, uint32_t waves, hr_result* out,

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libhrsearch.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "hrsearch.h")
 
 HR_OK, HR_EINVAL, HR_ECAPACITY, HR_EDEVICE, HR_ENOMEM = 0, -1, -2, -3, -4
+HR_WAVES_FILL = 0xFFFFFFFF
 
 _lib = None
 

@@ -111,8 +111,9 @@ def _run(ctx, dp, items_t, first, count_items, W, delta, waves, out, cap, count,
 
 
 def device_waves() -> int:
-    props = torch.cuda.get_device_properties(0)
-    return props.multi_processor_count * 8
+    """Persistent grid size: every wave the device keeps resident (the
+    library queries the kernel's occupancy)."""
+    return _lib.HR_WAVES_FILL
 
 
 class Runner:

@@ -829,6 +829,24 @@ hr_status flush_stat_slots(hr_ctx* ctx, uint64_t* stats, hipStream_t st) {
     return launched();
 }
 
+// Waves of the persistent batched kernel that one device keeps resident at
+// once (occupancy per CU x CUs), queried once per instantiation and device.
+template <int L, int DEG>
+uint32_t resident_waves(int device) {
+    static uint32_t cache[64] = {};
+    if (device < 0 || device >= 64) return 0;
+    if (cache[device] == 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_items<L, DEG, true>, 64, 0) !=
+                hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) !=
+                hipSuccess)
+            return 0;
+        cache[device] = (uint32_t)(per_cu * cus);
+    }
+    return cache[device];
+}
+
 hr_status ensure_scratch(hr_ctx* ctx, size_t bytes) {
     if (ctx->scratch_bytes >= bytes) return HR_OK;
     if (ctx->scratch) {
@@ -1065,10 +1083,17 @@ hr_status hr_batch_run(hr_ctx* ctx, const uint64_t* pool, const hr_item* items, 
     if (waves > 0) {
         k_zero_u32<<<1, 1, 0, st>>>(next);
         if ((s = launched()) != HR_OK) return s;
-        const uint32_t grid = waves < n_items ? waves : n_items;
-        HR_DISPATCH(width_bits, degree,
-                    (k_items<L_, D_, true><<<dim3(grid), dim3(64), 0, st>>>(
-                        pool, items, n_items, next, out, cap, cnt, sts)));
+        HR_DISPATCH(width_bits, degree, ({
+            uint32_t w = waves;
+            if (w == HR_WAVES_FILL) {   // as many waves as the device keeps resident
+                const uint32_t r = resident_waves<L_, D_>(ctx->device);
+                if (r == 0) return HR_EDEVICE;
+                w = r;
+            }
+            const uint32_t grid = w < n_items ? w : n_items;
+            k_items<L_, D_, true><<<dim3(grid), dim3(64), 0, st>>>(pool, items, n_items, next,
+                                                                   out, cap, cnt, sts);
+        }));
     } else {
         HR_DISPATCH(width_bits, degree,
                     (k_items<L_, D_, false><<<dim3(n_items), dim3(64), 0, st>>>(
