@@ -102,7 +102,7 @@ def main():
     pool = None
     if args.probe:
         args.no_serve = True
-    if not args.no_serve:
+    else:
         # preparation workers come from a forkserver started before the GPU is used
         from paper_1211_3056_amd import serve
         pool = serve.make_pool(args.prep_workers)
@@ -119,7 +119,7 @@ def main():
         return
     spec = JobSpec(**synth.CONFIG3)
     t0 = time.time()
-    P = prepare(spec)
+    P = prepare(spec, pool=pool)
     prep_s = time.time() - t0
     table, win, thr = pipeline.upload(P)
     ctx = api.context()

@@ -264,16 +264,35 @@ class SubPreparer:
         return table, win, thr
 
 
-def prepare(spec: JobSpec, subs=None) -> Prepared:
-    """Tables, windows and thresholds for the given sub-intervals (default all)."""
-    subs = np.arange(spec.n_sub, dtype=np.int64) if subs is None else np.asarray(subs, np.int64)
-    uf = output_ulp(spec)
+def _prepare_rows(spec: JobSpec, subs: np.ndarray, uf):
     sp = SubPreparer(spec.fname, spec.X0, spec.s, spec.mode, spec.delta, spec.W, uf)
     tables = np.zeros((len(subs), spec.entries, spec.limbs), np.uint64)
     win = np.zeros((len(subs), 2), np.uint64)
     thr = np.zeros((len(subs), 4), np.uint64)
     for row, t in enumerate(subs):
         tables[row], win[row], thr[row] = sp.prepare(int(t) * spec.per_sub, spec.per_sub, spec.N)
+    return tables, win, thr
+
+
+def _prepare_chunk(args):
+    spec, subs, uf = args
+    return _prepare_rows(spec, subs, uf)
+
+
+def prepare(spec: JobSpec, subs=None, pool=None) -> Prepared:
+    """Tables, windows and thresholds for the given sub-intervals (default
+    all).  pool: an optional process pool (concurrent.futures); the
+    sub-intervals are then prepared in chunks by its workers.  The result
+    does not depend on the pool."""
+    subs = np.arange(spec.n_sub, dtype=np.int64) if subs is None else np.asarray(subs, np.int64)
+    uf = output_ulp(spec)
+    workers = getattr(pool, "_max_workers", 0) if pool is not None else 0
+    if workers > 1 and len(subs) >= 2 * workers:
+        chunks = np.array_split(subs, 4 * workers)
+        parts = list(pool.map(_prepare_chunk, [(spec, c, uf) for c in chunks if len(c)]))
+        tables, win, thr = (np.concatenate([p[i] for p in parts]) for i in range(3))
+    else:
+        tables, win, thr = _prepare_rows(spec, subs, uf)
     with mpmath.workprec(64):
         h = _ulp(spec.X0)
     return Prepared(spec, subs, tables, win, thr, h, uf)

@@ -53,14 +53,17 @@ class Prepared:
         return int(self.tables.nbytes + self.items.nbytes + RESULT_RESERVE)
 
 
-def prepare_job(job: BatchJob, target_item_ns: float = 2000.0) -> Prepared:
-    """Plan and prepare one job (runs in a worker process)."""
+def prepare_job(job: BatchJob, target_item_ns: float = 2000.0, part=None) -> Prepared:
+    """Plan and prepare one job (runs in a worker process); part = (lo, hi)
+    restricts it to sub-intervals lo..hi-1 (see merge_parts)."""
     t0 = time.time()
     pj = plan_job(job)
     sp = SubPreparer(job.fname, job.X0, job.s, job.mode, pj.delta, pj.W, pj.uf)
     tables, rows = [], []
     off = 0
-    for t, s in enumerate(pj.subs):
+    lo, hi = part if part is not None else (0, len(pj.subs))
+    for t in range(lo, hi):
+        s = pj.subs[t]
         table, win, thr = sp.prepare(s.start, s.length, s.N)
         cand = s.length * float(win[1]) / 2.0 ** 64
         last_piece = s.pieces - 1 if s.length % s.N else 0xFFFFFFFF
@@ -70,8 +73,36 @@ def prepare_job(job: BatchJob, target_item_ns: float = 2000.0) -> Prepared:
                          t, piece0, npieces, nu, s.N, last_piece, last_N))
         tables.append(table.reshape(-1))
         off += table.size
-    return Prepared(job, pj.delta, pj.W, str(pj.uf), [(s.start, s.length, s.N) for s in pj.subs],
+    return Prepared(job, pj.delta, pj.W, str(pj.uf),
+                    [(s.start, s.length, s.N) for s in pj.subs[lo:hi]],
                     np.concatenate(tables), np.array(rows, dtype=ITEM_DTYPE), time.time() - t0)
+
+
+def merge_parts(parts) -> Prepared:
+    """One Prepared from the parts of a job prepared over consecutive
+    sub-interval ranges, in order: tables concatenated, item table offsets
+    moved accordingly (item sub indices are already global)."""
+    if len(parts) == 1:
+        return parts[0]
+    items, base = [], 0
+    for p in parts:
+        it = p.items.copy()
+        it["table"] += base
+        base += p.tables.size
+        items.append(it)
+    p0 = parts[0]
+    return Prepared(p0.job, p0.delta, p0.W, p0.uf, [s for p in parts for s in p.subs],
+                    np.concatenate([p.tables for p in parts]), np.concatenate(items),
+                    max(p.prep_s for p in parts))
+
+
+def job_parts(job: BatchJob, subs_per_part: int):
+    """Sub-interval ranges (lo, hi) of a job, for preparation by several
+    workers; one range for jobs of at most subs_per_part sub-intervals."""
+    n = -(-job.count // job.sub_len)
+    if n <= subs_per_part:
+        return [None]
+    return [(lo, min(lo + subs_per_part, n)) for lo in range(0, n, subs_per_part)]
 
 
 def decide_results(prep: Prepared, res: np.ndarray) -> np.ndarray:
@@ -105,6 +136,8 @@ class JobState:
     records: np.ndarray | None = None   # result records, device order (plan.canonical sorts)
     error: str = ""
     dev: object = None            # device handle of the admitted job (backend-specific)
+    parts: list = field(default_factory=list)   # prepared parts while preparing
+    left: int = 0                 # parts still being prepared
 
     @property
     def latency(self) -> float:
@@ -188,9 +221,10 @@ class Server:
     """Continuous-batching server over a device backend."""
 
     def __init__(self, backend, pool, hbm_budget: int | None = None, max_resident: int = 4096,
-                 clock=time.perf_counter):
+                 clock=time.perf_counter, subs_per_part: int = 16):
         self.backend = backend
         self.pool = pool
+        self.subs_per_part = subs_per_part   # large jobs are prepared by several workers
         self.budget = hbm_budget if hbm_budget is not None else int(0.9 * backend.free_memory())
         self.max_resident = max_resident
         self.clock = clock
@@ -225,18 +259,32 @@ class Server:
                     ready.append(st)
                     continue
                 st.status = "preparing"
-                futures[self.pool.submit(prepare_job, st.job)] = st
+                # split a large job over several workers only while workers
+                # are idle: it cuts that job's latency, not the throughput
+                idle = len(futures) < getattr(self.pool, "_max_workers", 1)
+                parts = job_parts(st.job, self.subs_per_part) if idle else [None]
+                st.parts, st.left = [None] * len(parts), len(parts)
+                for i, part in enumerate(parts):
+                    futures[self.pool.submit(prepare_job, st.job, 2000.0, part)] = (st, i)
             # finished preparations -> ready queue (arrival order kept by FIFO of completion)
             for fut in [f for f in futures if f.done()]:
-                st = futures.pop(fut)
+                st, i = futures.pop(fut)
+                if st.status == "failed":    # another part of it failed already
+                    continue
                 try:
-                    st.prep = fut.result()
+                    st.parts[i] = fut.result()
+                except Exception as e:       # a bad job fails alone
+                    st.status, st.error, st.t_done = "failed", repr(e), now()
+                    st.parts = []
+                    done += 1
+                    continue
+                st.left -= 1
+                if st.left == 0:
+                    st.prep = merge_parts(st.parts)
+                    st.parts = []
                     st.status = "ready"
                     st.t_ready = now()
                     ready.append(st)
-                except Exception as e:       # a bad job fails alone
-                    st.status, st.error, st.t_done = "failed", repr(e), now()
-                    done += 1
             ready.sort(key=lambda s: s.arrival)
             # admission by footprint and resident slots
             while ready:

@@ -120,3 +120,18 @@ def test_workload_generators_are_seeded():
     assert c5 == synth.config5(n_jobs=50)
     for d in c5:
         output_ulp_range(d["fname"], d["X0"], d["count"])     # one output binade each
+
+
+def test_prepare_with_pool_equals_serial():
+    """Sub-intervals prepared in chunks by worker processes give the same
+    tables, windows and thresholds as the serial loop."""
+    from paper_1211_3056_amd import serve
+    spec = JobSpec("exp", 1.0, 1 << 26, 24, "rn", 1 << 12, 1 << 8, 3, 192)
+    pool = serve.make_pool(2)
+    try:
+        a, b = prepare(spec), prepare(spec, pool=pool)
+    finally:
+        pool.shutdown()
+    assert spec.n_sub >= 4
+    for f in ("tables", "win", "thr", "subs"):
+        assert np.array_equal(getattr(a, f), getattr(b, f))

@@ -135,3 +135,28 @@ def test_split_by_job_equals_filter():
             want = r[r["job"] == jid]
             assert got.tobytes() == want.tobytes()          # device order kept
             assert canonical(got).tobytes() == canonical(want).tobytes()
+
+
+def test_parts_merge_to_the_whole_job():
+    """A job prepared as ranges of sub-intervals and merged equals the job
+    prepared in one piece (tables, items with their table offsets, subs)."""
+    job = BatchJob("sin", 1.25, 5 * (1 << 16) + 123, 12, "rn", sub_len=1 << 16, N=[1000, 777, 4096, 333, 5000, 64], job_id=3)
+    whole = serve.prepare_job(job)
+    parts = serve.job_parts(job, 2)
+    assert parts == [(0, 2), (2, 4), (4, 6)]
+    merged = serve.merge_parts([serve.prepare_job(job, part=p) for p in parts])
+    assert np.array_equal(merged.tables, whole.tables)
+    assert merged.items.tobytes() == whole.items.tobytes()
+    assert merged.subs == whole.subs and (merged.delta, merged.W) == (whole.delta, whole.W)
+    assert serve.job_parts(job, 16) == [None]
+
+
+def test_served_in_parts_equals_whole(pool):
+    be = FakeBackend()
+    jobs = [BatchJob("exp", 1.0 + 0.01 * i, 9 * (1 << 14), 20, "rn", sub_len=1 << 14, N=1 << 8, job_id=i) for i in range(3)]
+    a = serve.Server(be, pool, hbm_budget=1 << 30, subs_per_part=2).serve(jobs, np.zeros(3), realtime=False)
+    b = serve.Server(be, pool, hbm_budget=1 << 30, subs_per_part=64).serve(jobs, np.zeros(3), realtime=False)
+    for x, y in zip(a, b):
+        assert x.status == y.status == "done"
+        assert np.array_equal(x.prep.tables, y.prep.tables)
+        assert x.prep.items.tobytes() == y.prep.items.tobytes()
