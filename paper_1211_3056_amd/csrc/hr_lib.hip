@@ -13,6 +13,8 @@
 // division per quotient estimate.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include <stdint.h>
 #include <stdlib.h>
 
@@ -833,18 +835,20 @@ hr_status flush_stat_slots(hr_ctx* ctx, uint64_t* stats, hipStream_t st) {
 // once (occupancy per CU x CUs), queried once per instantiation and device.
 template <int L, int DEG>
 uint32_t resident_waves(int device) {
-    static uint32_t cache[64] = {};
+    static std::atomic<uint32_t> cache[64];   // zero-initialised (static storage)
     if (device < 0 || device >= 64) return 0;
-    if (cache[device] == 0) {
+    uint32_t w = cache[device].load(std::memory_order_relaxed);
+    if (w == 0) {
         int per_cu = 0, cus = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_items<L, DEG, true>, 64, 0) !=
                 hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) !=
                 hipSuccess)
             return 0;
-        cache[device] = (uint32_t)(per_cu * cus);
+        w = (uint32_t)(per_cu * cus);
+        cache[device].store(w, std::memory_order_relaxed);
     }
-    return cache[device];
+    return w;
 }
 
 hr_status ensure_scratch(hr_ctx* ctx, size_t bytes) {

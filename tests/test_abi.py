@@ -49,3 +49,30 @@ def test_record_layouts():
         assert getattr(_lib.hr_item, name).offset == api.ITEM_DTYPE.fields[name][1]
     for name, _ in _lib.hr_result._fields_:
         assert getattr(_lib.hr_result, name).offset == api.RESULT_DTYPE.fields[name][1]
+
+
+def _params():
+    """Parameter count of every function the header declares."""
+    text = open(_lib.HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    out = {}
+    for name, args in re.findall(r"\b(hr_[a-z_0-9]+)\s*\(([^)]*)\)\s*;", text):
+        args = args.strip()
+        out[name] = 0 if args in ("", "void") else args.count(",") + 1
+    return out
+
+
+def test_binding_argument_counts_match_header():
+    L = _lib.lib()
+    for name, n in _params().items():
+        assert len(getattr(L, name).argtypes) == n, name
+
+
+def test_header_constants_match_binding():
+    text = open(_lib.HEADER).read()
+    fill = int(re.search(r"#define HR_WAVES_FILL\s+(0x[0-9a-fA-F]+)u", text).group(1), 16)
+    assert fill == _lib.HR_WAVES_FILL
+    codes = dict(re.findall(r"\b(HR_E[A-Z]+|HR_OK)\s*=\s*(-?\d+)", text))
+    assert {k: int(v) for k, v in codes.items()} == {
+        "HR_OK": _lib.HR_OK, "HR_EINVAL": _lib.HR_EINVAL, "HR_ECAPACITY": _lib.HR_ECAPACITY,
+        "HR_EDEVICE": _lib.HR_EDEVICE, "HR_ENOMEM": _lib.HR_ENOMEM}
