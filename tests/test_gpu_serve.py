@@ -79,3 +79,17 @@ def test_small_budget_admission_on_device(pool):
     ref = serve.Server(be, pool).serve(jobs, np.zeros(len(jobs)), realtime=False)
     for a, b in zip(states, ref):
         assert canonical(a.records).tobytes() == canonical(b.records).tobytes()
+
+
+def test_serving_workload_sizes_sampled_against_oracle(pool):
+    """Jobs of the serving workload at their real sizes (2^24..2^36
+    arguments, eps 2^-20 or 2^-28), 200 of them with Poisson arrivals; the
+    five smallest against the oracle, every job complete."""
+    from paper_1211_3056_amd import serve
+    from paper_1211_3056_amd.plan import BatchJob, plan_job
+    jobs = [BatchJob(**d) for d in synth.config5(n_jobs=200)]
+    be = serve.GpuBackend()
+    states = serve.Server(be, pool).serve(jobs, synth.poisson_arrivals(len(jobs), rate=2000.0))
+    assert all(s.status == "done" for s in states), [s.error for s in states if s.error]
+    for st in sorted(states, key=lambda s: s.job.count)[:5]:
+        assert st.hr.tolist() == oracle_job(plan_job(st.job)), st.job
