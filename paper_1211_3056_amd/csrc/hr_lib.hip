@@ -333,6 +333,13 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
 
 constexpr int kQueue = 512;
 
+// Lanes of a fused wave take interleaved pieces: lane l owns pieces
+// l, l + kStride, l + 2 kStride, .. of its range, so the 64 lanes of one
+// step search 64 adjacent pieces, whose slopes a (and so the partial
+// quotients of the walk) nearly agree; consecutive pieces would spread a
+// wave over 64 nu of them.
+constexpr int kStride = 64;
+
 // Where a queued candidate comes from: result identifiers and thresholds.
 struct Origin {
     uint32_t job, sub, piece;
@@ -500,9 +507,9 @@ __device__ __forceinline__ bool top_rejects(const uint32_t* s_rows, const uint32
     }
 }
 
-// The per-wave body of the fused pass.  Each lane owns a packet of up to nu
-// consecutive pieces (cnt of them live, starting at piece p_begin) of the
-// wave's sub-interval and keeps the low entries of its difference table in
+// The per-wave body of the fused pass.  Each lane owns up to nu pieces
+// p_begin + kStride s (cnt of them live) of the wave's sub-interval and
+// keeps the low entries of their difference table with step kStride in
 // registers, advanced by one tabulated-difference step per piece.  For its
 // current piece a lane runs the exact degree-1 search; candidates are
 // compacted into an LDS queue (ballot + mbcnt) next to the piece rows, and
@@ -525,7 +532,7 @@ __device__ __forceinline__ void fused_wave(
         it.done = true;
         uint32_t steps = 0;
         if (live) {
-            const uint64_t piece = p_begin + s;
+            const uint64_t piece = p_begin + (uint64_t)kStride * s;
             const uint32_t n = (piece == last_piece) ? last_N : N;
             const uint64_t bb = top64(v[low_entry(DEG, 0, 0)]) - wlo;
             uint64_t aa;
@@ -612,21 +619,94 @@ __device__ __forceinline__ void fused_wave(
     }
 }
 
-// Low entries of every row at piece i0 of table T (inactive lanes: zero).
+// Forward differences with step h from those with step 1 (E = 1 + Delta):
+// Delta_h^m = (E^h - 1)^m = (sum_{i>=1} C(h, i) Delta^i)^m = sum_k a[m][k]
+// Delta^k, for polynomials of degree <= 6.  a[m][m] = h^m; every entry for
+// h = 64 is below 2^40.
+struct StrideCoef {
+    uint64_t a[7][7];
+};
+__host__ __device__ constexpr StrideCoef stride_coef(uint64_t h) {
+    StrideCoef c{};
+    uint64_t base[7] = {0, 0, 0, 0, 0, 0, 0};   // C(h, i)
+    uint64_t b = 1;
+    for (int i = 1; i <= 6; ++i) {
+        b = b * (h - (uint64_t)(i - 1)) / (uint64_t)i;
+        base[i] = b;
+    }
+    c.a[0][0] = 1;
+    for (int m = 1; m <= 6; ++m)
+        for (int k = m; k <= 6; ++k)
+            for (int i = 1; i <= k - m + 1; ++i) c.a[m][k] += c.a[m - 1][k - i] * base[i];
+    return c;
+}
+constexpr StrideCoef kStrideCoef = stride_coef(kStride);
+static_assert(kStrideCoef.a[1][1] == 64 && kStrideCoef.a[2][2] == 4096, "stride coefficients");
+
+// acc += x * c mod 2^(32 L) for a 64-bit c.
+template <int L>
+__device__ __forceinline__ void wmac64(hr::Word<L>& acc, const hr::Word<L>& x, uint64_t c) {
+    const uint32_t m[2] = {(uint32_t)c, (uint32_t)(c >> 32)};
+    hr::wmac_n<L, 2>(acc, x, m);
+}
+
+// Row J's low entries with step 1 (v[0..LEN), LEN = DEG - J) and its
+// constant top entry (top) -> the same row with step kStride, in place
+// (entry m only reads entries >= m).
+template <int L, int DEG, int J>
+__device__ __forceinline__ void row_to_stride(hr::Word<L>* v, const uint32_t* top) {
+    constexpr int LEN = DEG - J;
+    if constexpr (LEN > 1) {
+        hr::Word<L> t;
+        lds_word<L>(top, t);
+#pragma unroll
+        for (int m = 1; m < LEN; ++m) {
+            hr::Word<L> acc;
+            hr::wzero(acc);
+#pragma unroll
+            for (int k = m; k < LEN; ++k) wmac64<L>(acc, v[k], kStrideCoef.a[m][k]);
+            wmac64<L>(acc, t, kStrideCoef.a[m][LEN]);
+            v[m] = acc;
+        }
+    }
+}
+
+// s_top[j] *= kStride^(DEG - j): the constant top entries with step
+// kStride.  Whole wave; ends with a barrier.
+template <int L, int DEG>
+__device__ __forceinline__ void scale_top(uint32_t* s_top) {
+    __syncthreads();
+    if (threadIdx.x <= DEG) {
+        const int j = threadIdx.x;
+        hr::Word<L> t, acc;
+        lds_word<L>(s_top + j * L, t);
+        hr::wzero(acc);
+        wmac64<L>(acc, t, kStrideCoef.a[DEG - j][DEG - j]);
+#pragma unroll
+        for (int w = 0; w < L; ++w) s_top[j * L + w] = acc.w[w];
+    }
+    __syncthreads();
+}
+
+// Low entries of every row at piece i0 of table T, with step kStride
+// (inactive lanes: zero); s_top (loaded by load_top) is rescaled to step
+// kStride as well.  Whole wave.
 template <int L, int DEG>
 __device__ __forceinline__ void start_low(const uint64_t* __restrict__ T, uint64_t i0, bool active,
-                                          hr::Word<L>* v) {
+                                          hr::Word<L>* v, uint32_t* s_top) {
     if (active) {
         uint32_t cb[DEG][4];
         binom_limbs<DEG>(i0, cb);
         static_for<0, DEG>([&](auto J) {
             constexpr int j = decltype(J)::value;
             row_start_low<L, DEG, j>(T, cb, v + low_entry(DEG, j, 0));
+            row_to_stride<L, DEG, j>(v + low_entry(DEG, j, 0), s_top + j * L);
         });
     } else {
 #pragma unroll
         for (int e = 0; e < n_low(DEG); ++e) hr::wzero(v[e]);
     }
+    scale_top<L, DEG>(s_top);
 }
 
 // Statistics are summed per wave, then added into one of kStatSlots
@@ -658,10 +738,11 @@ __device__ __forceinline__ void flush_stats(unsigned long long* slots, uint64_t 
     }
 }
 
-// Whole sub-intervals of one uniform job (hr_pipeline).  Sub-interval s has
-// per_sub = ceil(tau / nu) packets, handled by wps = ceil(per_sub / 64)
-// consecutive waves (one workgroup each), so every wave works inside one
-// sub-interval: packet (b mod wps) 64 + lane of sub-interval b / wps.
+// Whole sub-intervals of one uniform job (hr_pipeline).  Sub-interval s is
+// handled by wps = ceil(tau / (64 nu)) consecutive waves (one workgroup
+// each), so every wave works inside one sub-interval: wave b covers pieces
+// [w 64 nu, (w + 1) 64 nu) of sub-interval b / wps, w = b mod wps, lane l
+// its pieces w 64 nu + l + 64 s.
 template <int L, int DEG>
 __global__ __launch_bounds__(64) void k_pipeline(
     const uint64_t* __restrict__ table, uint32_t n_sub, uint32_t tau, uint32_t nu, uint32_t wps,
@@ -673,17 +754,16 @@ __global__ __launch_bounds__(64) void k_pipeline(
     __shared__ uint32_t s_qlane[kQueue];
     __shared__ uint32_t s_qk[kQueue];
     const int lane = threadIdx.x;
-    const uint32_t per_sub = (tau + nu - 1) / nu;
     const uint32_t sub = blockIdx.x / wps;                 // < n_sub (grid = n_sub wps)
-    const uint32_t packet0 = (blockIdx.x % wps) * 64;
-    const uint32_t packet = packet0 + lane;
-    const bool active = packet < per_sub;
-    const uint64_t i0 = (uint64_t)packet * nu;
-    const uint32_t cnt = active ? (uint32_t)hr::umin(nu, tau - i0) : 0;
+    const uint64_t base = (uint64_t)(blockIdx.x % wps) * kStride * nu;
+    const uint64_t i0 = base + lane;
+    const bool active = i0 < tau;
+    const uint32_t cnt =
+        active ? (uint32_t)hr::umin(nu, (tau - i0 + kStride - 1) / kStride) : 0;
     const uint64_t* T = table + (uint64_t)sub * n_entries(DEG) * (L / 2);
     load_top<L, DEG>(T, s_top);
     hr::Word<L> v[n_low(DEG)];
-    start_low<L, DEG>(T, i0, active, v);
+    start_low<L, DEG>(T, i0, active, v, s_top);
     const uint64_t wlo = win[2 * (uint64_t)sub];
     const uint64_t wd = win[2 * (uint64_t)sub + 1];
     uint64_t n_pieces = 0, n_cand = 0, n_res = 0, n_steps = 0, n_slots = 0, n_full = 0;
@@ -691,7 +771,7 @@ __global__ __launch_bounds__(64) void k_pipeline(
         Origin o;
         o.job = 0;
         o.sub = sub;
-        o.piece = (packet0 + src) * nu + s;
+        o.piece = (uint32_t)(base + src + (uint64_t)kStride * s);
         o.thr = thr + 4 * (uint64_t)sub;
         return o;
     };
@@ -725,20 +805,21 @@ __global__ __launch_bounds__(64) void k_items(
     }
     while (idx < n_items) {
         const hr_item* I = items + idx;
-        const uint32_t nu = I->nu;
-        const uint64_t p_begin = (uint64_t)I->piece0 + (uint64_t)lane * nu;
+        const uint32_t nu = I->nu;                  // npieces <= 64 nu
+        const uint64_t p_begin = (uint64_t)I->piece0 + lane;
         const uint64_t p_end = (uint64_t)I->piece0 + I->npieces;
         const bool active = p_begin < p_end;
-        const uint32_t cnt = active ? (uint32_t)hr::umin(nu, p_end - p_begin) : 0;
+        const uint32_t cnt =
+            active ? (uint32_t)hr::umin(nu, (p_end - p_begin + kStride - 1) / kStride) : 0;
         const uint64_t* T = pool + I->table;
         load_top<L, DEG>(T, s_top);
         hr::Word<L> v[n_low(DEG)];
-        start_low<L, DEG>(T, p_begin, active, v);
+        start_low<L, DEG>(T, p_begin, active, v, s_top);
         auto origin = [&](uint32_t src, uint32_t s) {
             Origin o;
             o.job = I->job;
             o.sub = I->sub;
-            o.piece = I->piece0 + src * nu + s;
+            o.piece = I->piece0 + src + kStride * s;
             o.thr = I->thr;
             return o;
         };
