@@ -153,61 +153,72 @@ HR_HD void closest_left(uint64_t a, uint64_t b, uint32_t n, Near& r) {
         // Both quotients of a half step share one divisor and so one
         // reciprocal, and their remainders are the new length and the new
         // distance of b.
+        // A lane leaves the loop at the half step whose configuration would
+        // reach n points, with that step's quotients kept; the cut at n and
+        // the final neighbours are then worked out after the loop, once for
+        // every lane that stopped in a p step and once for those that
+        // stopped in a q step (lanes stop at different passes).
+        bool q_step = false;       // the stopping step reduced q (else p)
+        bool in_x = false;         // b sits in an interval that step splits
+        uint32_t sb = 0;           // b's quotient in that step
+        uint64_t rb = 0;           // and its remainder
         for (;;) {
             // ---- p > q: p-intervals (left ends < iq) get points at p - q, p - 2q, ..
             ++steps;
             const Recip Rq = recip(q);
-            uint64_t rp, rb;
+            uint64_t rp;
             k = quot_rem(p, Rq, n, rp);
-            const bool in_p = X < iq;
+            in_x = X < iq;
             // the first new point at or left of b: s = ceil((p - d) / q)
-            // = s1 + 1, and b's distance to it is q - 1 - rb
-            const uint32_t s1 = quot_rem(in_p ? p - d - 1 : 0, Rq, n, rb);
+            // = sb + 1, and b's distance to it is q - 1 - rb
+            sb = quot_rem(in_x ? p - d - 1 : 0, Rq, n, rb);
             const uint64_t kiq = (uint64_t)k * iq;
-            if (ip + iq + kiq >= n) {
-                // last configuration: only points with index < n exist
-                const uint64_t s = (uint64_t)s1 + 1;
-                if (in_p && s <= k && X + ip + s * iq < n) {
-                    X += ip + (uint32_t)(s * iq);
-                    d = q - 1 - rb;
-                }
-                const uint32_t su = (uint32_t)umin(k, idx_div(n - 1 - ip, iq));
-                v = iq;
-                beta = q;
-                u = ip + su * iq;
-                alpha = p - (uint64_t)su * q;
-                break;
-            }
-            const bool take = in_p && s1 < k;
-            X = take ? X + ip + (s1 + 1) * iq : X;
+            if (ip + iq + kiq >= n) break;
+            const bool take = in_x && sb < k;
+            X = take ? X + ip + (sb + 1) * iq : X;
             d = take ? q - 1 - rb : d;
             p = rp;
             ip += (uint32_t)kiq;
             // ---- q > p: q-intervals (left ends >= iq) get points at p, 2p, ..
             ++steps;
             const Recip Rp = recip(p);
-            uint64_t rq, rd;
+            uint64_t rq;
             k = quot_rem(q, Rp, n, rq);
-            const bool in_q = X >= iq;
-            // b's interval is shorter than q, so s2 = floor(d / p) <= k
-            const uint32_t s2 = quot_rem(in_q ? d : 0, Rp, n, rd);
+            in_x = X >= iq;
+            // b's interval is shorter than q, so sb = floor(d / p) <= k
+            sb = quot_rem(in_x ? d : 0, Rp, n, rb);
             const uint64_t kip = (uint64_t)k * ip;
             if (ip + iq + kip >= n) {
-                uint64_t s = s2;
-                if (X + s * ip > n - 1) s = idx_div(n - 1 - X, ip);
-                X += (uint32_t)(s * ip);
-                d -= s * p;
-                const uint32_t sv = (uint32_t)umin(k, idx_div(n - 1 - iq, ip));
-                u = ip;
-                alpha = p;
-                v = iq + sv * ip;
-                beta = q - (uint64_t)sv * p;
+                q_step = true;
                 break;
             }
-            X += s2 * ip;
-            d = in_q ? rd : d;
+            X += sb * ip;
+            d = in_x ? rb : d;
             q = rq;
             iq += (uint32_t)kip;
+        }
+        // last configuration: only points with index < n exist
+        if (!q_step) {
+            const uint64_t s = (uint64_t)sb + 1;
+            if (in_x && s <= k && X + ip + s * iq < n) {
+                X += ip + (uint32_t)(s * iq);
+                d = q - 1 - rb;
+            }
+            const uint32_t su = (uint32_t)umin(k, idx_div(n - 1 - ip, iq));
+            v = iq;
+            beta = q;
+            u = ip + su * iq;
+            alpha = p - (uint64_t)su * q;
+        } else {
+            uint64_t s = sb;
+            if (X + s * ip > n - 1) s = idx_div(n - 1 - X, ip);
+            X += (uint32_t)(s * ip);
+            d -= s * p;
+            const uint32_t sv = (uint32_t)umin(k, idx_div(n - 1 - iq, ip));
+            u = ip;
+            alpha = p;
+            v = iq + sv * ip;
+            beta = q - (uint64_t)sv * p;
         }
     }
     r.x = X;
