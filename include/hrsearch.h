@@ -177,7 +177,8 @@ typedef struct {
     uint32_t sub;       /* copied into results                           */
     uint32_t piece0;    /* first piece of the item                       */
     uint32_t npieces;   /* number of pieces (>= 1)                       */
-    uint32_t nu;        /* pieces per lane: npieces <= 64 * nu            */
+    uint32_t nu;        /* pieces per lane: npieces <= 64 * nu (lane l of  */
+                        /* the item's wave takes pieces l, l + 64, ..)    */
     uint32_t N;         /* arguments per piece                           */
     uint32_t last_piece;
     uint32_t last_N;

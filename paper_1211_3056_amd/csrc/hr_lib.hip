@@ -5,12 +5,15 @@
 //   k_tabulate                                       pieces (a, b)
 //   k_recheck                                        exact candidate values
 //   k_pipeline                                       fused tabulate+search+recheck
+//   k_items                                          the same over work items
+//                                                    (batched, persistent)
+//   k_zero_u32, k_stats_flush, k_quot_check          counters, diagnostics
 //
 // Every kernel maps one lane to one independent unit of work (an instance,
-// a packet of pieces, a candidate): the search is embarrassingly parallel
-// over sub-domains (Sec. 1.2 of the paper).  Nothing here is a dense
-// contraction; all arithmetic is 32/64-bit integer VALU work plus one f64
-// division per quotient estimate.
+// a set of pieces, a candidate): the search is embarrassingly parallel over
+// sub-domains (Sec. 1.2 of the paper).  Nothing here is a dense
+// contraction; all arithmetic is 32/64-bit integer VALU work plus binary64
+// quotient estimates.
 #include <hip/hip_runtime.h>
 
 #include <atomic>
