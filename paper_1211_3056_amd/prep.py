@@ -27,7 +27,6 @@ Transcendental values come from mpmath at W + guard + 64 bits.
 """
 from __future__ import annotations
 
-import math
 from dataclasses import dataclass
 from math import comb
 
