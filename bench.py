@@ -74,7 +74,7 @@ def parse():
 
 
 def ops_model(spec, pieces, cand, quotients, full):
-    """Algorithmic int32 VALU operations of one pass (see DESIGN.md):
+    """Algorithmic int32 VALU operations of one pass:
     tabulation: one 32-bit limb add per limb of each difference-row update,
     sum_j (delta - j) W/32 per piece; search: 96 ops per partial quotient of
     the exact closest-point walk plus 12 per candidate step; recheck: each
