@@ -76,3 +76,70 @@ def test_header_constants_match_binding():
     assert {k: int(v) for k, v in codes.items()} == {
         "HR_OK": _lib.HR_OK, "HR_EINVAL": _lib.HR_EINVAL, "HR_ECAPACITY": _lib.HR_ECAPACITY,
         "HR_EDEVICE": _lib.HR_EDEVICE, "HR_ENOMEM": _lib.HR_ENOMEM}
+
+
+def _gpu_visible():
+    import torch
+    return torch.cuda.is_available()
+
+
+@pytest.mark.skipif(_gpu_visible(), reason="stand-in context is only safe where no device exists")
+def test_each_parameter_check_returns_before_the_device():
+    """One invalid parameter per call, every other argument plausible: each
+    entry point rejects it on the host.  The context is a zeroed stand-in
+    and the buffers are host memory; a check that let the call through would
+    reach hipSetDevice, which fails here (no device) with HR_EDEVICE instead
+    of HR_EINVAL.  Empty inputs return HR_OK the same way."""
+    L = _lib.lib()
+    ctx = ctypes.create_string_buffer(256)
+    buf = ctypes.create_string_buffer(1 << 12)
+    c, p = ctypes.addressof(ctx), ctypes.addressof(buf)
+    E, OK, DEV = _lib.HR_EINVAL, _lib.HR_OK, _lib.HR_EDEVICE
+    big = (1 << 32) - 1                     # big^5 >= 2^128, big^4 < 2^128
+
+    def tab(deg=3, tau=16, width=128, table=p, n_sub=1):
+        return L.hr_tabulate(c, table, n_sub, deg, tau, width, p, p, None)
+    assert tab() == DEV             # all valid: reaches the device
+    for kw in ({"deg": 0}, {"deg": 7}, {"width": 64}, {"width": 320}, {"tau": 0},
+               {"deg": 5, "tau": big}, {"table": None}):
+        assert tab(**kw) == E, kw
+    assert tab(n_sub=0) == OK
+
+    def rck(deg=3, tau=16, width=128, max_k=100, thr=p, n_cand=1):
+        return L.hr_recheck(c, p, 1, deg, tau, width, p, p, n_cand, max_k, thr, p, p, None)
+    assert rck() == DEV
+    for kw in ({"deg": 7}, {"width": 0}, {"tau": 0}, {"deg": 5, "max_k": big},
+               {"deg": 5, "tau": big}, {"thr": None}):
+        assert rck(**kw) == E, kw
+    assert rck(n_cand=0) == OK
+
+    def pip(deg=3, tau=16, width=128, N=1 << 10, win=p, out=p, cap=1, count=p, n_sub=1):
+        return L.hr_pipeline(c, p, n_sub, deg, tau, width, N, win, p, out, cap, count, None, None)
+    assert pip() == DEV
+    for kw in ({"deg": 0}, {"width": 192 + 1}, {"tau": 0}, {"N": 0}, {"deg": 5, "N": big},
+               {"count": None}, {"win": None}, {"out": None}):
+        assert pip(**kw) == E, kw
+    assert pip(out=None, cap=0) == DEV     # no output wanted: no buffer needed
+    assert pip(n_sub=0) == OK
+
+    def qck(cap=1 << 10, out=p, n=1):
+        return L.hr_quot_check(c, p, p, cap, out, None, n, None)
+    assert qck() == DEV
+    for kw in ({"cap": 0}, {"cap": 1 << 32}, {"out": None}):
+        assert qck(**kw) == E, kw
+    assert qck(n=0) == OK
+
+    def bat(n_items=1, width=128, deg=3, items=p, out=p, cap=1, count=p):
+        return L.hr_batch_run(c, p, items, n_items, width, deg, 0, out, cap, count, None, None)
+    assert bat() == DEV
+    for kw in ({"n_items": 1 << 31}, {"deg": 0}, {"width": 100}, {"count": None},
+               {"items": None}, {"out": None}):
+        assert bat(**kw) == E, kw
+    assert bat(n_items=0) == OK
+
+    def sch(n=1, group=1, win_d=p, total=p, hits=p, cap=1, counts=p):
+        return L.hr_search(c, p, p, p, n, p, win_d, group, counts, p, hits, p, cap, total, None)
+    assert sch() == DEV
+    for kw in ({"group": 0}, {"n": 1 << 32}, {"win_d": None}, {"total": None},
+               {"hits": None}, {"counts": None}):
+        assert sch(**kw) == E, kw
