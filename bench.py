@@ -96,8 +96,9 @@ def ops_model(spec, pieces, cand, quotients, full):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); every "
-              "box in this setup has a single MI355X", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the search "
+              "shards by sub-interval with no communication, and that split is a design, "
+              "not a measured path", file=sys.stderr)
         sys.exit(2)
     pool = None
     if args.probe:
