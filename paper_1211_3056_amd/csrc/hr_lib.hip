@@ -227,17 +227,26 @@ constexpr uint32_t kMaxNu = 16;   // pieces per lane (pick_nu never exceeds it)
 // outputs of a wave's lanes form one contiguous range of the flattened
 // (sub-interval, piece) order (a lane is followed by the next packet of its
 // sub-interval, or by the first packet of the next one), so the pieces are
-// staged in LDS and written back as coalesced runs rather than as 64
-// strided streams.  LDS index of range position e: e + e / 16 (a pad word
-// every 16 entries keeps the strided staging writes off a single bank).
+// staged in LDS and written back as runs of consecutive pieces rather than
+// as 64 strided streams.  The staging holds kPart pieces per lane at a time
+// (slot = lane kPart + s, at LDS index slot + slot / kPart: one pad entry
+// per lane keeps the lanes' staging writes on distinct banks), so a packet
+// of nu pieces goes out in ceil(nu / kPart) parts; half a packet's worth of
+// LDS per wave leaves room for more resident waves per CU.  Where L x DEG
+// <= 32 (L 32-bit limbs per word: W = 256 with degree 4, or less) the
+// kernel is held to 128 VGPRs, 4 waves per SIMD (a few bytes of scratch at
+// W = 256, degree 4), so a grid of one wave per sub-interval fits the
+// device in one round.
+constexpr uint32_t kPart = kMaxNu / 2;
 template <int L, int DEG>
-__global__ __launch_bounds__(64) void k_tabulate(const uint64_t* __restrict__ table,
-                                                uint32_t n_sub, uint32_t tau, uint32_t nu,
-                                                uint64_t* __restrict__ a_out,
-                                                uint64_t* __restrict__ b_out) {
-    constexpr uint32_t kStage = 64 * kMaxNu + 64 * kMaxNu / 16;
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(L * DEG <= 32 ? 4 : 1)))
+void k_tabulate(const uint64_t* __restrict__ table, uint32_t n_sub, uint32_t tau, uint32_t nu,
+                uint64_t* __restrict__ a_out, uint64_t* __restrict__ b_out) {
+    constexpr uint32_t kStage = 64 * kPart + 64;
     __shared__ uint64_t s_a[kStage];
     __shared__ uint64_t s_b[kStage];
+    __shared__ uint32_t s_e0[64];
+    __shared__ uint32_t s_cnt[64];
     const int lane = threadIdx.x;
     const uint64_t gid = (uint64_t)blockIdx.x * 64 + lane;
     const uint64_t per_sub = (tau + nu - 1) / nu;
@@ -252,27 +261,37 @@ __global__ __launch_bounds__(64) void k_tabulate(const uint64_t* __restrict__ ta
     }
     const uint64_t wbase = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(base >> 32)) << 32) |
                            (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)base);
-    const uint32_t total = (uint32_t)wave_sum(cnt);   // <= 64 nu
+    s_e0[lane] = (uint32_t)(base - wbase);   // offset of the lane's packet in the range
+    s_cnt[lane] = cnt;                         // 0 for inactive lanes
+    hr::Word<L> v0[DEG + 1], v1[DEG];
     if (active) {
         const uint64_t* T = table + sub * n_entries(DEG) * (L / 2);
-        hr::Word<L> v0[DEG + 1], v1[DEG];
         uint32_t cb[DEG][4];
         binom_limbs<DEG>(i0, cb);
         row_start<L, DEG, 0>(T, cb, v0);
         row_start<L, DEG, 1>(T, cb, v1);
-        const uint32_t e0 = (uint32_t)(base - wbase);
-        for (uint32_t s = 0; s < cnt; ++s) {
-            const uint32_t e = e0 + s;
-            s_b[e + e / 16] = top64(v0[0]);
-            s_a[e + e / 16] = neg_top64(v1[0]);
-            row_step<L, DEG + 1>(v0);
-            row_step<L, DEG>(v1);
-        }
     }
-    __syncthreads();
-    for (uint32_t e = lane; e < total; e += 64) {
-        b_out[wbase + e] = s_b[e + e / 16];
-        a_out[wbase + e] = s_a[e + e / 16];
+    for (uint32_t p0 = 0; p0 < nu; p0 += kPart) {   // uniform: nu is a kernel argument
+        if (active) {
+            const uint32_t end = (uint32_t)hr::umin(cnt, p0 + kPart);
+            for (uint32_t s = p0; s < end; ++s) {
+                const uint32_t slot = (uint32_t)lane * kPart + (s - p0);
+                s_b[slot + slot / kPart] = top64(v0[0]);
+                s_a[slot + slot / kPart] = neg_top64(v1[0]);
+                row_step<L, DEG + 1>(v0);
+                row_step<L, DEG>(v1);
+            }
+        }
+        __syncthreads();
+        for (uint32_t slot = lane; slot < 64 * kPart; slot += 64) {
+            const uint32_t src = slot / kPart, s = p0 + slot % kPart;
+            if (s < s_cnt[src]) {
+                const uint64_t e = wbase + s_e0[src] + s;
+                b_out[e] = s_b[slot + slot / kPart];
+                a_out[e] = s_a[slot + slot / kPart];
+            }
+        }
+        __syncthreads();
     }
 }
 
