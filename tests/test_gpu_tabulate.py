@@ -101,6 +101,35 @@ def test_tabulate_config3_full_size_sampled():
             assert (int(a[t * spec.tau + i]), int(b[t * spec.tau + i])) == (ra, rb)
 
 
+@pytest.mark.parametrize("W,delta,n_sub,tau", [(256, 4, 4200, 1001), (192, 3, 4200, 1000),
+                                               (128, 2, 262144, 9)])
+def test_tabulate_long_packets_ragged(W, delta, n_sub, tau):
+    """Inputs large enough for 16 pieces per lane, staged in two parts of 8,
+    with sub-intervals that end inside a packet (tau = 1001: a last packet of
+    9, the second part holding one piece; tau = 1000: a last packet of 8, no
+    second part; tau = 9: every packet split 8 + 1).  Every output is written
+    (none keeps the fill value) and sampled pieces equal the oracle's."""
+    from paper_1211_3056_amd import _lib, api
+    # the library takes 16 pieces per lane once that still leaves 2^18 lanes
+    assert n_sub * -(-tau // 16) >= 1 << 18
+    tabs = synth.random_tables(77 * W + tau, n_sub, delta, W)
+    fill = 0x5A5A5A5A5A5A5A5A                    # below 2^63: the same bits as int64
+    a = torch.full((n_sub * tau,), fill, dtype=torch.int64, device="cuda").view(torch.uint64)
+    b = torch.full((n_sub * tau,), fill, dtype=torch.int64, device="cuda").view(torch.uint64)
+    _lib.hr_tabulate(api.context(), api.to_dev(tabs.reshape(-1), torch.uint64), n_sub, delta, tau,
+                     W, a, b)
+    a, b = a.cpu().numpy(), b.cpu().numpy()
+    assert not np.any(a == np.uint64(fill)) and not np.any(b == np.uint64(fill))
+    g = synth.rng(tau + W)
+    subs = sorted({0, 1, 63, 64, n_sub - 2, n_sub - 1} | set(g.integers(0, n_sub, 6).tolist()))
+    edge = [0, 1, 7, 8, 9, 15, 16, 17, tau - 9, tau - 8, tau - 2, tau - 1]
+    for t in subs:
+        T = _words(tabs[t:t + 1], delta)[0]
+        for i in sorted({i for i in edge if 0 <= i < tau} | set(g.integers(0, tau, 4).tolist())):
+            ra, rb = otab.piece_ab(otab.straightforward_rows(T, delta, int(i), W), W)
+            assert (int(a[t * tau + i]), int(b[t * tau + i])) == (ra, rb), (t, i)
+
+
 @pytest.mark.parametrize("W,delta,N", [(256, 4, 1 << 12), (192, 3, 1 << 14), (256, 6, 1 << 10),
                                        (128, 3, 1 << 14)])
 def test_fused_classes_at_threshold_boundaries(W, delta, N):
