@@ -107,18 +107,3 @@ def config_points(A: int, M: int, i: int, t: int) -> int:
     """Number of points q_i + q_{i-1,t} of configuration (i, t) (Eq. 2)."""
     e = expansion(A, M)
     return e.qq(i) + e.qq(i - 1) + t * e.qq(i)
-
-
-def closest_left(A: int, B: int, M: int, n: int):
-    """(distance, index) of the point {x a}, x < n, closest to the left of b.
-
-    Brute force over the n points: the quantity Sec. 4.1 says Lefevre's test
-    locates ("the multiple of a which is the closest to the left of b").
-    Ties cannot occur unless points coincide; the smallest index is returned.
-    """
-    best = None
-    for x in range(n):
-        d = (B - x * A) % M
-        if best is None or d < best[0]:
-            best = (d, x)
-    return best

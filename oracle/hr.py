@@ -38,13 +38,24 @@ from .taylor import (Job, arg_ulp, eps_approx, eps_round, f_value,
 M64 = 1 << 64
 
 
-def _is_hr(job: Job, m: int, uf, prec: int) -> bool:
-    eps = mpf(2) ** (-job.s)
+def distance(job: Job, m: int, uf=None, prec: int = 192) -> mpf:
+    """Distance of f(X)/u_f to the nearest breakpoint (Def. 2-3), X = X0 +
+    m h: to the nearest midpoint (Z + 1/2) in round-to-nearest mode, to
+    the nearest integer (representable number) in directed mode.  Computed
+    at `prec` bits; the caller keeps the mpmath context of that precision
+    to use it."""
+    uf = out_ulp(job) if uf is None else uf
     with mpmath.workprec(prec):
         X = mpf(job.X0) + m * arg_ulp(job.X0)
         y = f_value(job.fname, X) / uf
         z = y - (mpf(1) / 2 if job.mode == "rn" else 0)
-        dist = abs(z - mpmath.nint(z))
+        return abs(z - mpmath.nint(z))
+
+
+def _is_hr(job: Job, m: int, uf, prec: int) -> bool:
+    eps = mpf(2) ** (-job.s)
+    with mpmath.workprec(prec):
+        dist = distance(job, m, uf, prec)
         if abs(dist - eps) < mpf(2) ** (-(prec - 64)):
             if prec > 4096:
                 raise ArithmeticError("distance equals eps to 4096 bits")

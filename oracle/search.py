@@ -94,143 +94,140 @@ class LowerBound:
         return [t[0] for t in self.trace]
 
 
+# A two-length configuration (Sec. 3.2) is held as two sides: side 0 is the
+# length p with its count u, side 1 the length q with its count v (the
+# letters of Alg. 1-4).  Growing the configuration shortens one length by
+# the other (the Euclidean recurrences behind Eq. 2 and Eq. 3): the side
+# being shortened is called `r` below, the other one `o = 1 - r`.
+
+def _shorten(L, C, r, counts_to_r):
+    """Division-based step: L[r] loses floor(L[r] / L[o]) copies of L[o].
+
+    Each removed copy adds intervals on the other side; the count that grows
+    is C[r] (counts_to_r) or C[o], depending on which length each count is
+    attached to in the caller's convention.  Returns the quotient.
+    """
+    o = 1 - r
+    k = L[r] // L[o]
+    L[r] -= k * L[o]
+    if counts_to_r:
+        C[r] += k * C[o]
+    else:
+        C[o] += k * C[r]
+    return k
+
+
+def _snapshot(d, L, C):
+    return (d, L[0], L[1], C[0], C[1])
+
+
 def lefevre_alg1(A: int, B: int, N: int, eps: int, M: int = M64):
     """Lefevre's lower bound computation and test, Alg. 1 (Sec. 4.1).
 
-    p, q hold the two interval lengths, u, v their counts (u p + v q = 1,
-    Eq. 2), d the distance from b to the closest point on its left.  The
-    first branch reduces the length not containing b by division; the
-    second moves one point to the left of b by subtraction.  Returns on
-    u + v >= N (Success) or when d drops below eps (Failure: a point with
-    index < N lies within eps to the left of b).
+    Lengths p = {a} and q = 1 - {a} start with one interval each; d is the
+    distance from {b} to the closest placed point on its left.  One round:
+    if d >= p, a point has landed just left of b at distance p, so d drops
+    by p (Failure as soon as d < eps) and the p side is the one shortened;
+    otherwise the q side is.  The shortened side is first reduced by
+    division (configuration (i, t) -> (i + 1, 0)), the run exits with
+    Success once u + v >= N intervals exist, and then one subtraction step
+    ((i + 1, 0) -> (i + 1, 1)) moves a point towards b.  A zero length
+    means the points have become periodic (rational a): d is then final.
     """
-    p = A % M
-    q = M - p
+    L, C = [A % M, M - A % M], [1, 1]
     d = B % M
-    u, v = 1, 1
     it = 0
     trace = []
     if d < eps:
-        return LowerBound(False, d, u, v, it, trace)
-    if p == 0:   # every point sits at 0: d is already the exact minimum
-        return LowerBound(True, d, u, v, it, trace)
+        return LowerBound(False, d, C[0], C[1], it, trace)
+    if L[0] == 0:   # every point sits at 0: d is already the exact minimum
+        return LowerBound(True, d, C[0], C[1], it, trace)
     while True:
         it += 1
-        if d < p:
-            if p == 0:
-                return LowerBound(d >= eps, d, u, v, it, trace)
-            k = q // p
-            q -= k * p
-            u += k * v
-            if u + v >= N:
-                trace.append((d, p, q, u, v))
-                return LowerBound(True, d, u, v, it, trace)
-            p -= q
-            v += u
-        else:
-            d -= p
+        r = 0 if d >= L[0] else 1
+        if r == 0:
+            d -= L[0]
             if d < eps:
-                trace.append((d, p, q, u, v))
-                return LowerBound(False, d, u, v, it, trace)
-            if q == 0:
-                trace.append((d, p, q, u, v))
-                return LowerBound(True, d, u, v, it, trace)
-            k = p // q
-            p -= k * q
-            v += k * u
-            if u + v >= N:
-                trace.append((d, p, q, u, v))
-                return LowerBound(True, d, u, v, it, trace)
-            q -= p
-            u += v
-        trace.append((d, p, q, u, v))
+                trace.append(_snapshot(d, L, C))
+                return LowerBound(False, d, C[0], C[1], it, trace)
+        if L[1 - r] == 0:
+            if r == 0:
+                trace.append(_snapshot(d, L, C))
+            return LowerBound(d >= eps, d, C[0], C[1], it, trace)
+        _shorten(L, C, r, counts_to_r=False)
+        if C[0] + C[1] >= N:
+            trace.append(_snapshot(d, L, C))
+            return LowerBound(True, d, C[0], C[1], it, trace)
+        # one subtraction: the other side loses the new length r once
+        L[1 - r] -= L[r]
+        C[r] += C[1 - r]
+        trace.append(_snapshot(d, L, C))
+
+
+def _regular_round(L, C, d, r, printed):
+    """One partial quotient of the regular search (Alg. 2/4): the side r is
+    shortened by division and d, b's distance to the closest point on its
+    left, follows the split (Props. 1-2): after q shrinks, b's interval is
+    cut at multiples of p; after p shrinks, b moves on only if it lies
+    beyond the new p, and then modulo q.
+
+    The counts follow Eq. 3 (v p + u q = 1 after every round) unless
+    `printed`, which applies the updates as the listings print them."""
+    _shorten(L, C, r, counts_to_r=not printed)
+    if r == 1:
+        return d % L[0]
+    if d >= L[0]:
+        return (d - L[0]) % L[1]
+    return d
 
 
 def regular_alg2(A: int, B: int, N: int, eps: int, M: int = M64,
                  printed: bool = False):
     """New regular lower bound computation and test, Alg. 2 (Sec. 4.2).
 
-    Each iteration completes one partial quotient of the continued fraction
-    of a (division-based Euclid only, configurations (i, 0) of Eq. 3): the
-    shorter length reduces the longer one, and d is reduced modulo the new
-    length (Props. 1-2 give the side on which intervals split).  Returns
-    Success iff d >= eps once u + v >= N.
+    Starting from p = {a}, q = 1 and one interval, each round completes one
+    partial quotient of the continued fraction of a (division-based Euclid,
+    configurations (i, 0) of Eq. 3): whichever of p and q is longer is
+    shortened (see _regular_round).  Success iff d >= eps once the
+    configuration holds u + v >= N intervals; a zero length (rational a,
+    periodic points) ends the walk with d exact.
     """
-    p = A % M
-    q = M
+    L, C = [A % M, M], [1, 0]
     d = B % M
-    u, v = 1, 0
     it = 0
     trace = []
     if d < eps:
-        return LowerBound(False, d, u, v, it, trace)
+        return LowerBound(False, d, C[0], C[1], it, trace)
     while True:
-        if p < q:
-            if p == 0:
-                return LowerBound(d >= eps, d, u, v, it, trace)
-            it += 1
-            k = q // p
-            q -= k * p
-            if printed:
-                u += k * v
-            else:
-                v += k * u
-            d %= p
-        else:
-            if q == 0:
-                return LowerBound(d >= eps, d, u, v, it, trace)
-            it += 1
-            k = p // q
-            p -= k * q
-            if printed:
-                v += k * u
-            else:
-                u += k * v
-            if d >= p:
-                d = (d - p) % q
-        trace.append((d, p, q, u, v))
-        if u + v >= N:
-            return LowerBound(d >= eps, d, u, v, it, trace)
+        r = 1 if L[0] < L[1] else 0
+        if L[1 - r] == 0:
+            return LowerBound(d >= eps, d, C[0], C[1], it, trace)
+        it += 1
+        d = _regular_round(L, C, d, r, printed)
+        trace.append(_snapshot(d, L, C))
+        if C[0] + C[1] >= N:
+            return LowerBound(d >= eps, d, C[0], C[1], it, trace)
 
 
 def regular_alg4(A: int, B: int, N: int, eps: int, M: int = M64,
                  printed: bool = False):
-    """Regular test unrolled by two iterations, Alg. 4 (Sec. 4.3).
+    """Regular test unrolled by two rounds, Alg. 4 (Sec. 4.3).
 
-    Alg. 2's condition p < q alternates deterministically (true first, since
-    p starts at {a} and q at 1), so two half-steps per loop need no test on
-    which length to reduce.
+    In Alg. 2 the longer length alternates (q first, since p = {a} < 1), so
+    the rounds run in fixed pairs, q side then p side, without comparing
+    the lengths.
     """
-    p = A % M
-    q = M
+    L, C = [A % M, M], [1, 0]
     d = B % M
-    u, v = 1, 0
     it = 0
     trace = []
+    r = 1
     while True:
-        if p == 0:
-            return LowerBound(d >= eps, d, u, v, it, trace)
-        it += 1
-        k = q // p
-        q -= k * p
-        if printed:
-            u += k * v
-        else:
-            v += k * u
-        d %= p
-        trace.append((d, p, q, u, v))
-        if u + v >= N:
-            return LowerBound(d >= eps, d, u, v, it, trace)
-        if q == 0:
-            return LowerBound(d >= eps, d, u, v, it, trace)
-        k = p // q
-        p -= k * q
-        if printed:
-            v += k * u
-        else:
-            u += k * v
-        if d >= p:
-            d = (d - p) % q
-        trace.append((d, p, q, u, v))
-        if u + v >= N:
-            return LowerBound(d >= eps, d, u, v, it, trace)
+        if L[1 - r] == 0:
+            return LowerBound(d >= eps, d, C[0], C[1], it, trace)
+        it += r          # iterations count passes of the unrolled loop
+        d = _regular_round(L, C, d, r, printed)
+        trace.append(_snapshot(d, L, C))
+        if C[0] + C[1] >= N:
+            return LowerBound(d >= eps, d, C[0], C[1], it, trace)
+        r = 1 - r

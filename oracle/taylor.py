@@ -209,11 +209,16 @@ def eps_approx(job: Job, t: int) -> mpf:
 def eps_round(job: Job) -> mpf:
     """Upper bound on the effect of rounding the table entries to W bits.
 
-    Each entry is off by at most 2^-(W+1) (plus mpmath's error, far below);
-    piece i's r_j(i) sums C(i, l) of them, and the piece polynomial at x sums
-    C(x, j) of those, so the bound is 2^-W sum_j C(N-1, j) sum_l C(tau-1, l).
+    Each entry T[j][l] (j + l <= delta, the triangle of Fig. 6) is off by at
+    most 2^-(W+1), plus mpmath's error, which is far smaller.  Piece i's
+    r_j(i) = sum_l T[j][l] C(i, l) and the piece polynomial at x is
+    sum_j r_j(i) C(x, j) (Sec. 5.1-5.2), so the value at (i, x) moves by
+    sum_{j+l<=delta} C(x, j) C(i, l) entry errors at most; the binomials
+    grow with i and x, so the worst piece and argument are i = tau - 1,
+    x = N - 1.  The bound doubles that maximum to cover the half ulp and
+    mpmath's error together: 2^-W sum_{j+l<=delta} C(N-1, j) C(tau-1, l).
     """
     d = job.delta
-    sj = sum(comb(job.N - 1, j) for j in range(d + 1))
-    sl = sum(comb(job.tau - 1, l) for l in range(d + 1))
-    return mpf(2) ** (-job.W) * sj * sl
+    s = sum(comb(job.N - 1, j) * comb(job.tau - 1, l)
+            for j in range(d + 1) for l in range(d - j + 1))
+    return mpf(2) ** (-job.W) * s

@@ -5,7 +5,7 @@ Rigorous choices (results never depend on them, only speed does):
 * degree delta: smallest degree <= 4 whose Lagrange remainder over a whole
   sub-interval stays below eps 2^-12 (so that undecided values are rare);
 * word width W: smallest of 128, 192, 256 bits whose table-rounding bound
-  2^-W sum_j C(N-1, j) sum_l C(tau-1, l) stays below eps 2^-12 on every
+  2^-W sum_{j+l<=delta} C(N-1, j) C(tau-1, l) stays below eps 2^-12 on every
   sub-interval;
 * piece length N (when the job leaves it free): the power of two that
   minimises the modelled device time per argument, search cost
@@ -22,12 +22,11 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass
-from math import comb
 
 import mpmath
 from mpmath import mpf
 
-from .prep import _deriv_bound, _taylor_coeffs, _ulp, output_ulp_range
+from .prep import _deriv_bound, _taylor_coeffs, _ulp, output_ulp_range, round_sum
 
 WIDTHS = (128, 192, 256)
 MARGIN_BITS = 12
@@ -68,9 +67,7 @@ def choose_width(shapes, delta: int, s: int) -> int:
     """shapes: iterable of (N, tau) of the job's sub-intervals."""
     worst = 0
     for N, tau in set(shapes):
-        sj = sum(comb(N - 1, j) for j in range(delta + 1))
-        sl = sum(comb(tau - 1, l) for l in range(delta + 1))
-        worst = max(worst, sj * sl)
+        worst = max(worst, round_sum(N, tau, delta))
     need = s + MARGIN_BITS + worst.bit_length()
     for W in WIDTHS:
         if W >= need:

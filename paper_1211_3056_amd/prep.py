@@ -153,6 +153,23 @@ def _k_matrices(N: int, delta: int):
     return K
 
 
+def round_bound(N: int, tau: int, delta: int, W: int) -> mpf:
+    """Bound on how far rounding the table entries to W bits moves a piece
+    value.  Every entry T[j][l] (j + l <= delta) is within 2^-(W+1) of its
+    exact value (the fixed-point monomials carry guard bits, so their own
+    error is far smaller); the value of piece i at x is
+    sum_{j+l<=delta} T[j][l] C(i, l) C(x, j) (Sec. 5.1-5.2), whose
+    binomials peak at i = tau - 1, x = N - 1.  Twice that maximum:
+    2^-W sum_{j+l<=delta} C(N-1, j) C(tau-1, l)."""
+    return mpf(2) ** (-W) * round_sum(N, tau, delta)
+
+
+def round_sum(N: int, tau: int, delta: int) -> int:
+    """sum_{j+l<=delta} C(N-1, j) C(tau-1, l), the integer factor of round_bound."""
+    return sum(comb(N - 1, j) * comb(tau - 1, l)
+               for j in range(delta + 1) for l in range(delta - j + 1))
+
+
 @dataclass
 class Prepared:
     spec: JobSpec
@@ -231,8 +248,7 @@ class SubPreparer:
                     table[e, li] = (v >> (64 * li)) & (M64 - 1)
             # error budget of this sub-interval
             M = length
-            e_round = mpf(2) ** (-W) * sum(comb(N - 1, j) for j in range(d + 1)) \
-                * sum(comb(tau - 1, l) for l in range(d + 1))
+            e_round = round_bound(N, tau, d, W)
             e_row = mpf(2) ** (-W - 1) * sum(comb(tau - 1, l) for l in range(d + 1))
             nA = d + 1
             e_approx = _deriv_bound(self.fname, Xt, Xt + M * h, nA) * (M * h) ** nA \
@@ -256,11 +272,29 @@ class SubPreparer:
             s64 = mpf(2) ** 64
             win[0] = int(mpmath.floor(lo * s64)) % M64
             win[1] = min(int(mpmath.ceil(width * s64)) + 2, M64 - 1)
-            thr[0] = int(mpmath.ceil(mu * s64))
-            thr[1] = int(mpmath.floor((2 * eps - mu) * s64)) - 1
-            thr[2] = int(mpmath.ceil((2 * eps + mu) * s64))
-            thr[3] = int(mpmath.floor((1 - mu) * s64)) - 1
+            thr[:] = value_bands(mu, eps)
         return table, win, thr
+
+
+def value_bands(mu, eps):
+    """(hr_lo, hr_hi, rej_lo, rej_hi) on the top 64 bits t of an exact piece
+    value v = y - c + eps + e, |e| <= mu: HR for sure iff
+    mu <= t 2^-64 and t 2^-64 + 2^-64 <= 2 eps - mu, rejected for sure iff
+    2 eps + mu <= t 2^-64 and t 2^-64 + 2^-64 <= 1 - mu.  When the error
+    budget leaves no room for a band (mu too large for eps, a degree or
+    width too small for the job), that band is empty (lo = 2^64 - 1 > hi =
+    0): every candidate is then undecided and decided on the host."""
+    s64 = mpf(2) ** 64
+    hr_lo = int(mpmath.ceil(mu * s64))
+    hr_hi = int(mpmath.floor((2 * eps - mu) * s64)) - 1
+    rej_lo = int(mpmath.ceil((2 * eps + mu) * s64))
+    rej_hi = int(mpmath.floor((1 - mu) * s64)) - 1
+    out = []
+    for lo, hi in ((hr_lo, hr_hi), (rej_lo, rej_hi)):
+        if hi < lo or lo > M64 - 1 or hi < 0:
+            lo, hi = M64 - 1, 0
+        out += [max(lo, 0), min(hi, M64 - 1)]
+    return out
 
 
 def _prepare_rows(spec: JobSpec, subs: np.ndarray, uf):

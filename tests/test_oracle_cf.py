@@ -132,3 +132,27 @@ def test_prop1_next_configuration():
                 assert (r1[0], r1[1]) == (i, t + 1)
             else:
                 assert (r1[0], r1[1]) == (i + 1, 0)
+
+
+def test_config_points_gives_two_length_configurations():
+    """config_points(i, t) = q_i + q_{i-1,t} (Eq. 2): the brute-force point
+    set of that size has exactly the two lengths theta_i and theta_{i-1,t}
+    (Sec. 3.2), for Table 2's a = 14/45 and random fractions.  A count off
+    by one point, or without the t q_i term, yields three lengths."""
+    rng = random.Random(31)
+    cases = [(14, 45)] + [(rng.randrange(1, M), M) for M in (97, 1000, 4096, 65537)
+                          for _ in range(12)]
+    checked = 0
+    for A, M in cases:
+        e = cf.expansion(A, M)
+        i = 0
+        while e.th(i) != 0 and e.qq(i) + e.qq(i - 1) <= 3000:
+            for t in range(min(e.kk(i + 1), 6)):
+                n = cf.config_points(A, M, i, t)
+                if n > 3000:
+                    break
+                lengths = set(cf.gap_sequence(A, M, n))
+                assert lengths <= {e.th(i), e.th(i - 1) - t * e.th(i)}, (A, M, i, t)
+                checked += 1
+            i += 1
+    assert checked > 200

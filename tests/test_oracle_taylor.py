@@ -1,5 +1,6 @@
 """Pins for oracle/taylor.py (Sec. 3.1 change of variable, Sec. 5.1 tables)."""
 import random
+from math import comb
 
 import mpmath
 import pytest
@@ -104,7 +105,54 @@ def test_rounded_table_reproduces_g(fname, mode):
                 assert abs(diff) <= mu
 
 
-def test_eps_round_dominates_table_rounding():
+ROUND_SHAPES = [(1 << 16, 1 << 3, 3, 128), (2, 1 << 20, 3, 128), (1 << 9, 1 << 9, 4, 128),
+                (1 << 12, 1 << 6, 2, 192), (3, 5, 6, 256)]
+
+
+def _adversarial_rounding_error(N, tau, delta, W):
+    """Exact values of a random table placed exactly halfway between two
+    W-bit words, every entry rounded up (the worst a rounding to nearest
+    can do, all errors of one sign): the change of the value of the last
+    piece at its last argument, in units of 2^-(W+1), by the oracle's
+    straightforward shift and piece evaluation."""
+    rng = random.Random(N * 1000003 + tau)
+    half = [[2 * rng.randrange(1 << W) + 1 for _ in range(delta - j + 1)]
+            for j in range(delta + 1)]                      # units of 2^-(W+1)
+    up = [[((v + 1) // 2) % (1 << W) for v in row] for row in half]
+    i, x = tau - 1, N - 1
+    V = evaluate(straightforward_rows(up, delta, i, W), x, W)
+    exact = sum(half[j][l] * comb(i, l) * comb(x, j)
+                for j in range(delta + 1) for l in range(delta - j + 1))
+    err = (2 * V - exact) % (1 << (W + 1))
+    return err if err < 1 << W else err - (1 << (W + 1))
+
+
+@pytest.mark.parametrize("N,tau,delta,W", ROUND_SHAPES)
+def test_eps_round_reached_by_adversarial_rounding(N, tau, delta, W):
+    """eps_round bounds the worst rounding of a table and is reached within
+    its stated factor 2: the adversarial table of _adversarial_rounding_error
+    moves the value by exactly half of it.  Shapes with N >> tau and with
+    tau >> N make a bound without the C(N-1, j) or without the C(tau-1, l)
+    factor fail, and a product of the two full sums (instead of the
+    triangle j + l <= delta) is loose by far more than 4."""
+    err = _adversarial_rounding_error(N, tau, delta, W)
+    bound = eps_round(Job("exp", 1.0, N * tau, 20, "rn", N, tau, delta, W)) * mpf(2) ** (W + 1)
+    assert 0 < err <= bound
+    assert 4 * err >= bound
+
+
+@pytest.mark.parametrize("N,tau,delta,W", ROUND_SHAPES)
+def test_product_round_bound_reached_by_adversarial_rounding(N, tau, delta, W):
+    """The same pin for the device path's own bound (prep.round_bound),
+    which sets its windows and thresholds and the autotuner's width."""
+    from paper_1211_3056_amd.prep import round_bound
+    err = _adversarial_rounding_error(N, tau, delta, W)
+    bound = round_bound(N, tau, delta, W) * mpf(2) ** (W + 1)
+    assert 0 < err <= bound
+    assert 4 * err >= bound
+
+
+def test_eps_round_small_against_eps_approx():
     job = Job("exp", 1.0, 1 << 24, 24, "rn", 1 << 9, 1 << 5, 3, 128)
     assert eps_round(job) < mpf(2) ** -90
     assert eps_approx(job, 0) < mpf(2) ** -40

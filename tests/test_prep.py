@@ -94,7 +94,8 @@ def test_autotuner_choices():
     assert autotune.choose_degree("exp", 1.0, 1 << 20, 28, uf) <= 2
     # width grows with the table-rounding amplification
     assert autotune.choose_width([(1 << 12, 1 << 16)], 3, 28) == 128
-    assert autotune.choose_width([(1 << 20, 1 << 16)], 4, 32) >= 192
+    assert autotune.choose_width([(1 << 20, 1 << 16)], 4, 32) == 128
+    assert autotune.choose_width([(1 << 20, 1 << 16)], 6, 32) >= 192
     # piece length: tighter thresholds favour shorter pieces
     assert autotune.choose_N("exp", 1.0, 1 << 36, 28, uf) <= autotune.choose_N("exp", 1.0, 1 << 36, 20, uf)
     # item split covers every piece exactly once, 64 lanes x nu each
@@ -135,3 +136,32 @@ def test_prepare_with_pool_equals_serial():
     assert spec.n_sub >= 4
     for f in ("tables", "win", "thr", "subs"):
         assert np.array_equal(getattr(a, f), getattr(b, f))
+
+
+def test_error_budget_above_eps_gives_empty_hr_band():
+    """A degree too small for eps (degree 1 over 2^24 arguments of exp with
+    eps = 2^-8: the Lagrange remainder alone exceeds 2 eps) leaves no value
+    that can be certified HR: the HR band is empty (lo > hi) instead of
+    negative, and the reject band still holds the values far from every
+    breakpoint."""
+    uf = output_ulp_range("exp", 1.0, 1 << 24)
+    sp = SubPreparer("exp", 1.0, 8, "rn", 1, 128, uf)
+    _, win, thr = sp.prepare(0, 1 << 24, 1 << 12)
+    hr_lo, hr_hi, rej_lo, rej_hi = (int(x) for x in thr)
+    assert hr_lo == 2 ** 64 - 1 and hr_hi == 0
+    assert 0 < rej_lo < rej_hi < 2 ** 64
+    assert int(win[1]) > 2 ** 58          # the window covers the whole budget
+
+
+def test_value_bands_closed_forms():
+    from mpmath import mpf
+
+    from paper_1211_3056_amd.prep import value_bands
+    eps = mpf(2) ** -20
+    assert value_bands(mpf(0), eps) == [0, 2 ** 45 - 1, 2 ** 45, 2 ** 64 - 1]
+    # mu = 2^-30: HR band [2^34, 2^45 - 2^34 - 1], reject [2^45 + 2^34, 2^64 - 2^34 - 1]
+    mu = mpf(2) ** -30
+    assert value_bands(mu, eps) == [2 ** 34, 2 ** 45 - 2 ** 34 - 1, 2 ** 45 + 2 ** 34,
+                                    2 ** 64 - 2 ** 34 - 1]
+    assert value_bands(mpf(2) ** -19, eps)[:2] == [2 ** 64 - 1, 0]
+    assert value_bands(mpf(1) / 2, eps) == [2 ** 64 - 1, 0, 2 ** 64 - 1, 0]
