@@ -104,3 +104,31 @@ def evaluate(rows, k: int, W: int) -> int:
     for j, r in enumerate(rows):
         acc += r * comb(k, j)
     return acc & mask
+
+
+def round_to_width(x: int, Wu: int, W: int) -> int:
+    """A Wu-bit word rounded to the nearest W-bit word (W <= Wu), mod 2^W
+    (ties upwards)."""
+    if Wu == W:
+        return x % (1 << W)
+    return ((x + (1 << (Wu - W - 1))) >> (Wu - W)) % (1 << W)
+
+
+def subinterval_table(U, Du: int, t: int, N: int, delta: int, Wu: int, W: int):
+    """Initial table T_t[j][l] (j + l <= delta, W-bit words) of sub-interval
+    t, from the upper table U[n][m] of its range (two levels of the
+    hierarchical method, Sec. 5.1):
+
+      * straightforward shift in t (Sec. 5.2) one level up:
+        D_t[n] = sum_m U[n][m] C(t, m) mod 2^Wu, the step-1 differences of
+        the range's polynomial at the sub-interval's first argument;
+      * R_t(x) = sum_n D_t[n] C(x, n) (Newton form);
+      * the hierarchical table of R_t with steps 1 and N (Fig. 6), exact
+        mod 2^Wu, keeping j + l <= delta;
+      * every entry rounded once to the nearest W-bit word.
+    """
+    from .taylor import hierarchical_table
+    D = straightforward_rows(U, Du, t, Wu)
+    mask = (1 << Wu) - 1
+    T = hierarchical_table(lambda x: evaluate(D, x, Wu), delta, N)
+    return [[round_to_width(v & mask, Wu, W) for v in row] for row in T]

@@ -222,3 +222,34 @@ def eps_round(job: Job) -> mpf:
     s = sum(comb(job.N - 1, j) * comb(job.tau - 1, l)
             for j in range(d + 1) for l in range(d - j + 1))
     return mpf(2) ** (-job.W) * s
+
+
+# ---------------------------------------------------------------- upper level
+
+def upper_coeffs(fname: str, X0: float, count: int, s: int, mode: str, degree: int,
+                 prec: int):
+    """Monomial coefficients of the upper-level polynomial U of a whole range
+    (Sec. 5.1, the top of the hierarchy): the degree-`degree` Taylor
+    polynomial of g(x) = f(X0 + x h)/u_f - c + eps at x = 0, with u_f the
+    output ulp over the range (which must stay in one binade)."""
+    job = Job(fname, X0, count, s, mode, 1, count, degree, 128)
+    return taylor_coeffs(job, 0, prec)
+
+
+def upper_table(fname: str, X0: float, count: int, s: int, mode: str, degree: int,
+                S: int, Wu: int):
+    """Upper table of a range: U[n][m] = Delta_S^m Delta_1^n U(0) for
+    n + m <= degree (the hierarchical table of U with steps 1 and S, Sec.
+    5.1 and Fig. 6), each entry rounded once to the nearest Wu-bit fraction.
+    Sub-interval t of the range starts at argument t S."""
+    prec = Wu + 64 * degree + 512
+    with mpmath.workprec(prec):
+        c = upper_coeffs(fname, X0, count, s, mode, degree, prec)
+
+        def U(x):
+            x = mpf(x)
+            return sum(c[k] * x ** k for k in range(degree + 1))
+
+        T = hierarchical_table(U, degree, S)
+        return [[round_word(v, Wu) for v in row] for row in T]
+

@@ -2,6 +2,7 @@
 import random
 from math import comb
 
+import mpmath
 import numpy as np
 import pytest
 
@@ -129,3 +130,58 @@ def test_native_exhaustive_matches_python_scan(W, d):
         got = [(int(xs[pos + j]), int(cls[pos + j])) for j in range(int(counts[p]))]
         pos += int(counts[p])
         assert got == expect
+
+
+# ------------------------------------------------ two levels (Sec. 5.1) ---
+
+@pytest.mark.parametrize("Du,delta,Wu,W", [(3, 2, 192, 128), (6, 4, 320, 256), (6, 3, 320, 192)])
+def test_two_level_shift_of_integer_polynomials(Du, delta, Wu, W):
+    """For a polynomial V with integer coefficients (no rounding anywhere
+    above the last step), the sub-interval table obtained through the
+    upper table and the straightforward shift in t equals the hierarchical
+    table of x -> V(t S + x) computed directly, rounded to W bits."""
+    from oracle.tabulate import round_to_width, subinterval_table
+    from oracle.taylor import hierarchical_table
+    rng = random.Random(Du * 100 + delta)
+    S, N = 1 << 20, 1 << 9
+    coef = [rng.randrange(-(1 << 40), 1 << 40) for _ in range(Du + 1)]
+    V = lambda x: sum(c * x ** k for k, c in enumerate(coef))
+    mask = (1 << Wu) - 1
+    upper = [[v & mask for v in row] for row in hierarchical_table(V, Du, S)]
+    for t in (0, 1, 7, 1000, 4095):
+        got = subinterval_table(upper, Du, t, N, delta, Wu, W)
+        ref = hierarchical_table(lambda x: V(t * S + x), delta, N)
+        assert got == [[round_to_width(v & mask, Wu, W) for v in row] for row in ref], t
+
+
+def test_round_to_width_closed_forms():
+    from oracle.tabulate import round_to_width
+    assert round_to_width(0x17, 8, 4) == 0x1
+    assert round_to_width(0x18, 8, 4) == 0x2          # tie: upwards
+    assert round_to_width(0xF8, 8, 4) == 0x0          # wraps mod 2^4
+    assert round_to_width(0xAB, 8, 8) == 0xAB
+
+
+@pytest.mark.parametrize("fname,X0", [("exp", 1.0), ("log", 3.0), ("sin", 1.0)])
+def test_two_level_table_reproduces_g(fname, X0):
+    """Piece values from sub-interval tables made through the upper table
+    (degree 6 over 2^36 arguments, 320-bit words) equal g(t S + i N + x)
+    mod 1 to within 2^-56 at random points; the approximation, truncation
+    and rounding errors of this shape are all below 2^-63."""
+    from oracle.tabulate import subinterval_table
+    from oracle.taylor import Job, arg_ulp, f_value, out_ulp, upper_table
+    count, S, N, delta, Wu, W = 1 << 36, 1 << 24, 1 << 12, 3, 320, 192
+    upper = upper_table(fname, X0, count, 20, "rn", 6, S, Wu)
+    job = Job(fname, X0, count, 20, "rn", N, S // N, delta, W)
+    uf = out_ulp(job)
+    rng = random.Random(len(fname))
+    for _ in range(10):
+        t, i, x = rng.randrange(count // S), rng.randrange(S // N), rng.randrange(N)
+        T = subinterval_table(upper, 6, t, N, delta, Wu, W)
+        V = evaluate(straightforward_rows(T, delta, i, W), x, W)
+        with mpmath.workprec(300):
+            X = mpmath.mpf(X0) + (t * S + i * N + x) * arg_ulp(X0)
+            g = f_value(fname, X) / uf - mpmath.mpf(1) / 2 + mpmath.mpf(2) ** -20
+            diff = mpmath.mpf(V) / mpmath.mpf(2) ** W - (g - mpmath.floor(g))
+            diff -= mpmath.nint(diff)
+            assert abs(diff) < mpmath.mpf(2) ** -56, (t, i, x, diff)
