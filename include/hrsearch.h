@@ -47,6 +47,7 @@ extern "C" {
 
 #define HR_ABI_VERSION 1
 #define HR_MAX_DEGREE 6
+#define HR_MAX_UPPER_DEGREE 10     /* hr_subtables: degree of a range's polynomial */
 #define HR_WAVES_FILL 0xffffffffu   /* hr_batch_run: as many waves as stay resident */
 
 typedef struct hr_ctx hr_ctx;
@@ -232,6 +233,43 @@ hr_status hr_pipeline(hr_ctx* ctx, const uint64_t* table, uint32_t n_sub, uint32
 hr_status hr_batch_run(hr_ctx* ctx, const uint64_t* pool, const hr_item* items, uint32_t n_items,
                        uint32_t width_bits, uint32_t degree, uint32_t waves, hr_result* out,
                        uint64_t cap, uint64_t* count, uint64_t* stats, void* stream);
+
+/*
+ * hr_subtables -- initial tables of sub-intervals made on the device from
+ * the upper table of their range: the top two levels of the hierarchical
+ * method (Sec. 5.1 of the paper), one level up from hr_tabulate.
+ *
+ * A range's polynomial U (degree Du, typically 5-10) is given by its upper
+ * table U[n][m] = Delta_S^m Delta_1^n U(0), n + m <= Du, with S arguments per
+ * sub-interval, so that sub-interval t covers U(t S + y), y in [0, S).  For
+ * output table i < n_sub, with t = t_idx[i] (t0 + i when t_idx is NULL) and
+ * piece length N = N_per[i] (N when N_per is NULL):
+ *   D[n]    = sum_m U[n][m] C(t, m)   mod 1    (straightforward shift, Sec. 5.2:
+ *             the step-1 differences Delta_1^n R_t(0) of R_t(y) = U(t S + y))
+ *   T[j][l] = Delta_N^l Delta_1^j R_t(0) = sum_s (-1)^(l-s) C(l, s) sum_k C(s N, k) D[j+k]
+ *             mod 1, for j + l <= degree (entries of higher order are dropped:
+ *             the caller's error budget covers them),
+ * computed exactly at upper_width bits, then rounded to the nearest
+ * width_bits-bit word (ties upwards) and written in hr_tabulate's table
+ * layout at table_out + i E width_bits/64 (E = (degree+1)(degree+2)/2).
+ *
+ *  upper        uint64[E_u * upper_width/64], E_u = (Du+1)(Du+2)/2, entry
+ *               (n, m) at e(n, m) as in hr_tabulate with degree Du
+ *  upper_degree Du in 1..HR_MAX_UPPER_DEGREE
+ *  upper_width  192, 256, 320, 384 or 448 (>= width_bits)
+ *  t_idx, N_per uint32[n_sub] (device, may be NULL: see above)
+ *  max_t, max_N bounds on every t and N: max_t^Du < 2^128 and
+ *               (degree max_N)^Du < 2^upper_width are checked here; a table
+ *               whose t or N exceeds them (or N = 0) is written as zeros
+ *  degree, width_bits  of the output tables (degree <= Du, as hr_tabulate)
+ *  table_out    uint64[n_sub * E * width_bits/64] out
+ * Errors: HR_EINVAL for a parameter outside these ranges or a null pointer.
+ */
+hr_status hr_subtables(hr_ctx* ctx, const uint64_t* upper, uint32_t upper_degree,
+                       uint32_t upper_width, const uint32_t* t_idx, uint32_t t0,
+                       const uint32_t* N_per, uint32_t N, uint32_t max_t, uint32_t max_N,
+                       uint32_t n_sub, uint32_t degree, uint32_t width_bits, uint64_t* table_out,
+                       void* stream);
 
 /*
  * hr_quot_check -- diagnostic: the partial-quotient routine of the search,

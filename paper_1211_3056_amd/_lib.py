@@ -44,7 +44,7 @@ class hr_item(ctypes.Structure):
 RESULT_BYTES = ctypes.sizeof(hr_result)
 ITEM_BYTES = ctypes.sizeof(hr_item)
 EXPORTS = ("hr_abi_version", "hr_status_str", "hr_create", "hr_destroy", "hr_search", "hr_batch_run",
-           "hr_tabulate", "hr_recheck", "hr_pipeline", "hr_quot_check")
+           "hr_tabulate", "hr_recheck", "hr_pipeline", "hr_quot_check", "hr_subtables")
 
 
 def lib():
@@ -74,6 +74,8 @@ def lib():
     L.hr_pipeline.argtypes = [P, P, u32, u32, u32, u32, u32, P, P, P, u64, P, P, P]
     L.hr_quot_check.restype = i32
     L.hr_quot_check.argtypes = [P, P, P, u64, P, P, u64, P]
+    L.hr_subtables.restype = i32
+    L.hr_subtables.argtypes = [P, P, u32, u32, P, u32, P, u32, u32, u32, u32, u32, u32, P, P]
     L.hr_batch_run.restype = i32
     L.hr_batch_run.argtypes = [P, P, P, u32, u32, u32, u32, P, u64, P, P, P]
     _lib = L
@@ -164,6 +166,13 @@ def hr_batch_run(ctx, pool, items, n_items, width, degree, waves, out, cap, coun
     _check("hr_batch_run", lib().hr_batch_run(ctx.handle, _p(pool), _p(items), n_items, width,
                                               degree, waves, _p(out), cap, _p(count), _p(stats),
                                               _stream(stream)))
+
+
+def hr_subtables(ctx, upper, upper_degree, upper_width, t_idx, t0, N_per, N, max_t, max_N,
+                 n_sub, degree, width, table_out, stream=None):
+    _check("hr_subtables", lib().hr_subtables(ctx.handle, _p(upper), upper_degree, upper_width,
+                                              _p(t_idx), t0, _p(N_per), N, max_t, max_N, n_sub,
+                                              degree, width, _p(table_out), _stream(stream)))
 
 
 def hr_quot_check(ctx, num, den, cap, out, rem=None, stream=None):

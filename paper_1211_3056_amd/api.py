@@ -73,6 +73,28 @@ def tabulate(table, n_sub, degree, tau, width, ctx=None, stream=None):
     return a, b
 
 
+def subtables(upper, upper_degree, upper_width, n_sub, degree, width, N, t0=0, t_idx=None,
+              max_t=None, max_N=None, ctx=None, stream=None, out=None):
+    """Sub-interval tables from an upper table (hr_subtables).  N: an int
+    (every table) or a uint32 device tensor (one per table); t_idx: None
+    (tables t0 .. t0 + n_sub - 1) or a uint32 device tensor.  Returns the
+    uint64 table tensor (n_sub * E * width/64 limbs)."""
+    ctx = ctx or context()
+    dev = upper.device
+    E = (degree + 1) * (degree + 2) // 2
+    if out is None:
+        out = torch.empty(max(n_sub, 1) * E * (width // 64), dtype=torch.uint64, device=dev)
+    N_per = N if isinstance(N, torch.Tensor) else None
+    N0 = 0 if N_per is not None else int(N)
+    if max_t is None:
+        max_t = t0 + n_sub - 1 if t_idx is None else int(t_idx.to(torch.int64).max().item())
+    if max_N is None:
+        max_N = N0 if N_per is None else int(N_per.to(torch.int64).max().item())
+    _lib.hr_subtables(ctx, upper, upper_degree, upper_width, t_idx, t0, N_per, N0, max_t, max_N,
+                      n_sub, degree, width, out, stream)
+    return out
+
+
 def recheck(table, n_sub, degree, tau, width, cand_inst, cand_k, max_k, thr, ctx=None,
             stream=None):
     ctx = ctx or context()

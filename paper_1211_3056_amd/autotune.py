@@ -26,7 +26,8 @@ from dataclasses import dataclass
 import mpmath
 from mpmath import mpf
 
-from .prep import _deriv_bound, _taylor_coeffs, _ulp, output_ulp_range, round_sum
+from .prep import (MAX_UPPER_DEGREE, _deriv_bound, _taylor_coeffs, _ulp, output_ulp_range,
+                   round_sum, upper_error)
 
 WIDTHS = (128, 192, 256)
 MARGIN_BITS = 12
@@ -61,6 +62,17 @@ def choose_degree(fname: str, X0: float, sub_len: int, s: int, uf, max_delta: in
             if ea <= lim:
                 return d
     raise ValueError("no degree <= %d is accurate enough; use shorter sub-intervals" % max_delta)
+
+
+def choose_upper_degree(fname: str, X0: float, count: int, s: int, delta: int = 1) -> int:
+    """Smallest degree >= delta of a range's upper polynomial whose Lagrange
+    remainder over the whole range is below eps 2^-12."""
+    uf = output_ulp_range(fname, X0, count)
+    lim = mpf(2) ** (-s - MARGIN_BITS)
+    for Du in range(max(delta, 1), MAX_UPPER_DEGREE + 1):
+        if upper_error(fname, X0, count, Du, uf) <= lim:
+            return Du
+    raise ValueError("range too wide for one upper polynomial; split it")
 
 
 def choose_width(shapes, delta: int, s: int) -> int:

@@ -295,6 +295,150 @@ void k_tabulate(const uint64_t* __restrict__ table, uint32_t n_sub, uint32_t tau
     }
 }
 
+// ---------------------------------------------------------------- sub-interval tables
+
+// w *= x mod 2^(32 L) for a 64-bit x.
+template <int L>
+__device__ __forceinline__ void wmul_u64(hr::Word<L>& w, uint64_t x) {
+    hr::Word<L> acc;
+    hr::wzero(acc);
+    const uint32_t m[2] = {(uint32_t)x, (uint32_t)(x >> 32)};
+    hr::wmac_n<L, 2>(acc, w, m);
+    w = acc;
+}
+
+// w /= k for a w that k divides (k < 2^16): long division from the top
+// limb.  Each partial dividend r 2^32 + limb is below 2^48, so its binary64
+// quotient by k is exact enough that the floor is the integer quotient
+// (the fractional part is a multiple of 1/k, far from 1 - 2^-53 relative).
+template <int L>
+__device__ __forceinline__ void wdiv_exact(hr::Word<L>& w, uint32_t k) {
+    uint64_t r = 0;
+#pragma unroll
+    for (int i = L - 1; i >= 0; --i) {
+        const uint64_t cur = (r << 32) | w.w[i];
+        const uint64_t q = hr::idx_div(cur, k);
+        r = cur - q * k;
+        w.w[i] = (uint32_t)q;
+    }
+}
+
+// acc -= x mod 2^(32 L).
+template <int L>
+__device__ __forceinline__ void wsub(hr::Word<L>& acc, const hr::Word<L>& x) {
+    unsigned b = 0;
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        unsigned bo;
+        acc.w[i] = __builtin_subc(acc.w[i], x.w[i], b, &bo);
+        b = bo;
+    }
+}
+
+constexpr int kMaxUpperDegree = HR_MAX_UPPER_DEGREE;
+
+// One lane per (output table i, entry (j, l)) of the sub-interval tables
+// made from an upper table U of degree du (steps 1 and S, LU 32-bit limbs
+// per word).  With R_t(y) = U(t S + y) held by its step-1 differences
+// D[n] = Delta_1^n R_t(0) = sum_m U[n][m] C(t, m) (straightforward shift in
+// the sub-interval index, Sec. 5.2), the entry is
+//   T[j][l] = Delta_N^l Delta_1^j R_t(0)
+//           = sum_s (-1)^(l-s) C(l, s) r_j(s N),  r_j(y) = sum_k C(y, k) D[j+k],
+// exact mod 2^(32 LU), then rounded to the nearest W-bit word.  C(t, m) is
+// an exact 128-bit integer (t^du < 2^128) and C(s N, k) an exact LU-limb
+// integer ((deg N)^du < 2^(32 LU)); both are built one step at a time,
+// C(y, k) = C(y, k-1) (y - k + 1) / k.
+template <int LU>
+__global__ __launch_bounds__(64) void k_subtables(
+    const uint64_t* __restrict__ upper, uint32_t du, const uint32_t* __restrict__ t_idx,
+    uint32_t t0, const uint32_t* __restrict__ N_per, uint32_t N0, uint32_t max_t, uint32_t max_N,
+    uint32_t n_sub, uint32_t deg, uint32_t wbits, uint64_t* __restrict__ out) {
+    const uint32_t E = (deg + 1) * (deg + 2) / 2;
+    const uint64_t g = (uint64_t)blockIdx.x * 64 + threadIdx.x;
+    const uint64_t i = g / E;
+    if (i >= n_sub) return;
+    uint32_t e = (uint32_t)(g % E);
+    const uint32_t e_out = e;
+    uint32_t j = 0;
+    while (e > deg - j) {   // entry e of the (j, l) order
+        e -= deg - j + 1;
+        ++j;
+    }
+    const uint32_t l = e;
+    const uint32_t lw = wbits / 64;
+    uint64_t* dst = out + (i * E + e_out) * lw;
+    const uint32_t t = t_idx ? t_idx[i] : t0 + (uint32_t)i;
+    const uint32_t N = N_per ? N_per[i] : N0;
+    if (t > max_t || N == 0 || N > max_N) {
+        for (uint32_t w = 0; w < lw; ++w) dst[w] = 0;
+        return;
+    }
+    constexpr int LW = LU / 2;   // 64-bit limbs of an upper word
+    // D[j .. du] (only those entry (j, l) reads: D[j + k], k <= du - j)
+    hr::Word<LU> D[kMaxUpperDegree + 1];
+#pragma unroll
+    for (int k = 0; k <= kMaxUpperDegree; ++k) {
+        if (k > (int)(du - j)) break;
+        const uint32_t n = j + k;
+        hr::Word<LU> acc;
+        load_word<LU>(upper + (size_t)entry(du, n, 0) * LW, acc);
+        hr::Word<4> c;             // C(t, m), exact
+        hr::wzero(c);
+        c.w[0] = 1;
+#pragma unroll
+        for (int m = 1; m <= kMaxUpperDegree; ++m) {
+            if (m > (int)(du - n)) break;
+            wmul_u64<4>(c, (uint64_t)t - (uint64_t)(m - 1));
+            wdiv_exact<4>(c, (uint32_t)m);
+            hr::Word<LU> u;
+            load_word<LU>(upper + (size_t)entry(du, n, m) * LW, u);
+            hr::wmac128(acc, u, c.w);
+        }
+        D[k] = acc;
+    }
+    // T[j][l] = sum_s (-1)^(l-s) C(l, s) r_j(s N)
+    hr::Word<LU> T;
+    hr::wzero(T);
+    uint32_t cls = 1;   // C(l, s)
+    for (uint32_t s = 0; s <= l; ++s) {
+        if (s > 0) cls = cls * (l - s + 1) / s;
+        const uint64_t y = (uint64_t)s * N;
+        hr::Word<LU> r = D[0];
+        hr::Word<LU> c;            // C(y, k), exact
+        hr::wzero(c);
+        c.w[0] = 1;
+#pragma unroll
+        for (int k = 1; k <= kMaxUpperDegree; ++k) {
+            if (k > (int)(du - j)) break;
+            wmul_u64<LU>(c, y - (uint64_t)(k - 1));
+            wdiv_exact<LU>(c, (uint32_t)k);
+            hr::wmac_n<LU, LU>(r, D[k], c.w);
+        }
+        hr::Word<LU> rc;
+        hr::wzero(rc);
+        const uint32_t m1[1] = {cls};
+        hr::wmac_n<LU, 1>(rc, r, m1);
+        if ((l - s) & 1) wsub(T, rc);
+        else hr::wadd(T, rc);
+    }
+    // round to the nearest W-bit word (ties upwards), keep its W bits
+    const uint32_t drop = 32 * LU - wbits;   // bits below the kept word
+    if (drop > 0) {
+        hr::Word<LU> half;
+        hr::wzero(half);
+#pragma unroll
+        for (int w = 0; w < LU; ++w)
+            if ((uint32_t)w == (drop - 1) / 32) half.w[w] = 1u << ((drop - 1) % 32);
+        hr::wadd(T, half);
+    }
+    const uint32_t w0 = drop / 32;
+#pragma unroll
+    for (int w = 0; w < LU / 2; ++w) {
+        if ((uint32_t)w < lw)
+            dst[w] = ((uint64_t)T.w[w0 + 2 * w + 1] << 32) | T.w[w0 + 2 * w];
+    }
+}
+
 // ---------------------------------------------------------------- recheck
 
 template <int L>
@@ -551,7 +695,7 @@ __device__ __forceinline__ void fused_wave(
     for (uint32_t s = 0; s < nu; ++s) {
         const bool live = active && s < cnt;
         hr::HitIter it;
-        it.done = true;
+        hr::iter_init(it, 0, 0, 0, 0);   // every field defined; done (no points)
         uint32_t steps = 0;
         if (live) {
             const uint64_t piece = p_begin + (uint64_t)kStride * s;
@@ -981,6 +1125,23 @@ bool pow_fits128(uint64_t x, uint32_t deg) {
     return true;
 }
 
+// bit length of x^n (exact, x^n < 2^512)
+uint32_t pow_bits(uint64_t x, uint32_t n) {
+    uint32_t w[17] = {1};
+    for (uint32_t i = 0; i < n; ++i) {
+        uint64_t carry = 0;
+        for (int k = 0; k < 17; ++k) {
+            const unsigned __int128 p = (unsigned __int128)w[k] * x + carry;
+            w[k] = (uint32_t)p;
+            carry = (uint64_t)(p >> 32);
+        }
+        if (carry) return 1024;
+    }
+    for (int k = 16; k >= 0; --k)
+        if (w[k]) return 32 * k + 32 - __builtin_clz(w[k]);
+    return 0;
+}
+
 bool valid_poly(uint32_t degree, uint32_t width_bits) {
     return degree >= 1 && degree <= HR_MAX_DEGREE &&
            (width_bits == 128 || width_bits == 192 || width_bits == 256);
@@ -1159,6 +1320,43 @@ hr_status hr_pipeline(hr_ctx* ctx, const uint64_t* table, uint32_t n_sub, uint32
                     (unsigned long long*)count, stat_slots(ctx, stats))));
     const hr_status s = launched();
     return s != HR_OK ? s : flush_stat_slots(ctx, stats, st);
+}
+
+hr_status hr_subtables(hr_ctx* ctx, const uint64_t* upper, uint32_t upper_degree,
+                       uint32_t upper_width, const uint32_t* t_idx, uint32_t t0,
+                       const uint32_t* N_per, uint32_t N, uint32_t max_t, uint32_t max_N,
+                       uint32_t n_sub, uint32_t degree, uint32_t width_bits, uint64_t* table_out,
+                       void* stream) {
+    if (!ctx || upper_degree < 1 || upper_degree > HR_MAX_UPPER_DEGREE) return HR_EINVAL;
+    if (upper_width % 64 != 0 || upper_width < 192 || upper_width > 448) return HR_EINVAL;
+    if (!valid_poly(degree, width_bits) || degree > upper_degree || width_bits > upper_width)
+        return HR_EINVAL;
+    if (max_N == 0 || !pow_fits128(max_t, upper_degree) ||
+        pow_bits((uint64_t)degree * max_N, upper_degree) > upper_width)
+        return HR_EINVAL;
+    if (!t_idx && (uint64_t)t0 + n_sub - 1 > max_t && n_sub > 0) return HR_EINVAL;
+    if (!N_per && (N == 0 || N > max_N)) return HR_EINVAL;
+    if (n_sub == 0) return HR_OK;
+    if (!upper || !table_out) return HR_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return HR_EDEVICE;
+    const uint64_t lanes = (uint64_t)n_sub * ((degree + 1) * (degree + 2) / 2);
+    const uint64_t blocks = (lanes + 63) / 64;
+    if (blocks > 0xffffffffull) return HR_EINVAL;
+    hipStream_t st = as_stream(stream);
+#define HR_SUBTAB(LU_)                                                                    \
+    k_subtables<LU_><<<dim3((uint32_t)blocks), dim3(64), 0, st>>>(                        \
+        upper, upper_degree, t_idx, t0, N_per, N, max_t, max_N, n_sub, degree, width_bits, \
+        table_out)
+    switch (upper_width / 32) {
+        case 6: HR_SUBTAB(6); break;
+        case 8: HR_SUBTAB(8); break;
+        case 10: HR_SUBTAB(10); break;
+        case 12: HR_SUBTAB(12); break;
+        case 14: HR_SUBTAB(14); break;
+        default: return HR_EINVAL;
+    }
+#undef HR_SUBTAB
+    return launched();
 }
 
 hr_status hr_quot_check(hr_ctx* ctx, const uint64_t* num, const uint64_t* den, uint64_t cap,

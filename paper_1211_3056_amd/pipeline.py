@@ -4,6 +4,10 @@ prepare (host tables, windows, thresholds) -> device: either the fused
 kernel (hr_pipeline, one launch) or the plain launch chain
 (hr_tabulate -> hr_search -> hr_recheck) -> host decision of the few
 undecided values -> sorted HR offsets m (argument X0 + m h).
+
+With an upper table (``form="upper"``) the host prepares only the range's
+upper table and one window; the sub-interval tables are made on the device
+(hr_subtables) and fed to the fused kernel.
 """
 from __future__ import annotations
 
@@ -11,7 +15,7 @@ import numpy as np
 import torch
 
 from . import api
-from .prep import JobSpec, Prepared, is_hr, prepare
+from .prep import JobSpec, Prepared, is_hr, prepare, upper_table, upper_windows
 
 
 def upload(P: Prepared, device="cuda"):
@@ -67,6 +71,47 @@ def run_plain(P: Prepared, dev_args=None, ctx=None):
                 "results": int(keep.sum()), "undecided": n_und}
 
 
-def search_job(spec: JobSpec, form: str = "fused", subs=None, ctx=None):
+class UpperPrepared:
+    """Host part of a job whose sub-interval tables the device makes: the
+    range's upper table, and the window and thresholds shared by all its
+    sub-intervals (same fields as Prepared where the finish step reads them)."""
+
+    def __init__(self, spec: JobSpec, Du: int, Wu: int):
+        self.spec = spec
+        self.Du, self.Wu = Du, Wu
+        self.U = upper_table(spec.fname, spec.X0, spec.count, spec.s, spec.mode, spec.per_sub,
+                             Du, Wu)
+        self.win, self.thr, self.mu = upper_windows(self.U, spec.N, spec.tau, spec.delta, spec.W)
+        self.subs = np.arange(spec.n_sub, dtype=np.int64)
+        self.uf = self.U.uf
+
+
+def upload_upper(Pu: UpperPrepared, device="cuda"):
+    """Upper table, and per-sub-interval window and threshold arrays (the
+    shared values repeated), on the device."""
+    n = Pu.spec.n_sub
+    upper = api.to_dev(Pu.U.words.reshape(-1), torch.uint64, device)
+    win = api.to_dev(Pu.win, torch.uint64, device).repeat(n)
+    thr = api.to_dev(Pu.thr, torch.uint64, device).repeat(n)
+    return upper, win, thr
+
+
+def make_tables(Pu: UpperPrepared, upper, ctx=None, stream=None, out=None):
+    spec = Pu.spec
+    return api.subtables(upper, Pu.Du, Pu.Wu, spec.n_sub, spec.delta, spec.W, spec.N, ctx=ctx,
+                         stream=stream, out=out)
+
+
+def run_upper(Pu: UpperPrepared, ctx=None):
+    upper, win, thr = upload_upper(Pu)
+    table = make_tables(Pu, upper, ctx=ctx)
+    return run_fused(Pu, dev_args=(table, win, thr), ctx=ctx)
+
+
+def search_job(spec: JobSpec, form: str = "fused", subs=None, ctx=None, Du=None, Wu=320):
+    if form == "upper":
+        from .autotune import choose_upper_degree
+        Du = Du or choose_upper_degree(spec.fname, spec.X0, spec.count, spec.s, spec.delta)
+        return run_upper(UpperPrepared(spec, Du, Wu), ctx=ctx)
     P = prepare(spec, subs)
     return (run_fused if form == "fused" else run_plain)(P, ctx=ctx)

@@ -346,3 +346,176 @@ def is_hr(spec: JobSpec, m: int, uf=None, prec: int = 192) -> bool:
                 raise ArithmeticError("undecidable at 4096 bits")
             return is_hr(spec, m, uf, 2 * prec)
         return bool(dist < eps)
+
+
+# ---------------------------------------------------------------- upper level
+#
+# The top of the hierarchical method (Sec. 5.1): one polynomial U of higher
+# degree Du for a whole range, tabulated once on the host into its
+# hierarchical table with steps 1 and S (S = arguments per sub-interval);
+# the device turns it into every sub-interval's initial table (hr_subtables:
+# straightforward shift in the sub-interval index, Sec. 5.2, then the
+# sub-interval's table with steps 1 and N, truncated to degree delta and
+# rounded to W bits).  Only the upper table, one window and one set of
+# thresholds per piece length are made here, in place of one Taylor
+# expansion per sub-interval.
+
+UPPER_WIDTHS = (192, 256, 320, 384, 448)
+MAX_UPPER_DEGREE = 12
+
+
+_KCACHE: dict = {}
+
+
+def _kmat_cached(S: int, Du: int):
+    key = (S, Du)
+    if key not in _KCACHE:
+        K = _k_matrices(S, Du)
+        kmax = max(abs(v) for Kn in K for v in Kn.values())
+        _KCACHE[key] = (K, kmax.bit_length() + 96)
+    return _KCACHE[key]
+
+
+@dataclass
+class UpperTable:
+    fname: str
+    X0: float
+    count: int
+    s: int
+    mode: str
+    S: int                 # arguments per sub-interval (step of the table in x)
+    Du: int                # degree of U
+    Wu: int                # word width of the table entries
+    words: np.ndarray      # uint64 (E_u, Wu/64): entry (n, m) = Delta_S^m Delta_1^n U(0)
+    coeffs: list           # monomial coefficients of U (mpf), -c + eps folded into c_0
+    uf: object
+    e_approx: object       # |U(x) - g(x)| over the range (Lagrange remainder)
+
+    @property
+    def n_sub(self) -> int:
+        return -(-self.count // self.S)
+
+    def shift_error(self, n: int):
+        """Bound on the error of Delta_1^n R_t(0) = sum_m U[n][m] C(t, m) for
+        any sub-interval t < n_sub, from the rounding of U's entries to Wu
+        bits (twice 2^-(Wu+1), covering the guard bits' own error)."""
+        T = self.n_sub
+        return mpf(2) ** (-self.Wu) * sum(comb(T - 1, m) for m in range(self.Du - n + 1))
+
+
+def upper_error(fname: str, X0: float, count: int, Du: int, uf) -> mpf:
+    """Lagrange remainder of the degree-Du Taylor polynomial at X0 over the
+    whole range [X0, X0 + count h), in output ulps (closed-form bounds of
+    |f^(Du+1)|), with a 1% margin."""
+    with mpmath.workprec(128):
+        h = _ulp(X0)
+        n = Du + 1
+        return _deriv_bound(fname, mpf(X0), mpf(X0) + count * h, n) * (count * h) ** n \
+            / (mpmath.factorial(n) * uf) * mpf("1.01")
+
+
+def upper_table(fname: str, X0: float, count: int, s: int, mode: str, S: int, Du: int,
+                Wu: int, uf=None) -> UpperTable:
+    """Upper table of the range [X0, X0 + count h): the hierarchical table,
+    steps 1 and S, of the degree-Du Taylor polynomial U of
+    g(x) = f(X0 + x h)/u_f - c + eps at x = 0, each entry rounded once to
+    the nearest Wu-bit fraction (exact integer image of fixed-point
+    monomial coefficients, as for the sub-interval tables)."""
+    if fname not in FUNCTIONS or Wu not in UPPER_WIDTHS or not 1 <= Du <= MAX_UPPER_DEGREE:
+        raise ValueError("unsupported function, upper width or upper degree")
+    uf = output_ulp_range(fname, X0, count) if uf is None else uf
+    K, G = _kmat_cached(S, Du)
+    pairs = [(n, m) for n in range(Du + 1) for m in range(Du - n + 1)]
+    Lw = Wu // 64
+    words = np.zeros((len(pairs), Lw), np.uint64)
+    with mpmath.workprec(Wu + G + 64):
+        h = _ulp(X0)
+        eps = mpf(2) ** (-s)
+        c = _taylor_coeffs(fname, mpf(X0), Du, h, uf)
+        c[0] += eps - (mpf(1) / 2 if mode == "rn" else 0)
+        scale = mpf(2) ** (Wu + G)
+        C = [int(mpmath.nint(cn * scale)) for cn in c]
+    mask = (1 << Wu) - 1
+    for e, (n, m) in enumerate(pairs):
+        v = sum(C[k] * K[k][(n, m)] for k in range(Du + 1))
+        v = ((v + (1 << (G - 1))) >> G) & mask
+        for li in range(Lw):
+            words[e, li] = (v >> (64 * li)) & (M64 - 1)
+    return UpperTable(fname, X0, count, s, mode, S, Du, Wu, words, c, uf,
+                      upper_error(fname, X0, count, Du, uf))
+
+
+def upper_windows(U: UpperTable, N: int, tau: int, delta: int, W: int):
+    """Degree-1 window (lo, d), thresholds and error bound mu of every
+    sub-interval of the range whose table the device makes from U with
+    pieces of N arguments, tau pieces, degree delta and width W.
+
+    Write R_t(y) = U(t S + y) and R~_t = R_t + E_t for the polynomial the
+    device shifts out of the rounded upper table (E_t(y) = sum_n e_n C(y, n),
+    |e_n| <= U.shift_error(n)).  The sub-interval table keeps the entries
+    j + l <= delta of R~_t's table with steps 1 and N and rounds them to W
+    bits, so a piece value differs from g by at most
+      mu = e_approx(U)                                  (Lagrange remainder)
+         + sum_{j+l>delta} N^l max|U^(j+l)| C(tau-1, l) C(N-1, j)
+                                                        (dropped entries of R_t)
+         + sum_{j+l<=delta} |Delta_N^l Delta_1^j E_t(0)| C(tau-1, l) C(N-1, j)
+                                                        (kept entries of E_t)
+         + 2^-W sum_{j+l<=delta} C(N-1, j) C(tau-1, l)  (rounding to W bits),
+    using Delta_N^l Delta_1^j R_t(0) = N^l U^(j+l)(xi) (mean value form of
+    differences) and |Delta_N^l C(y, n-j)| <= 2^l C(l N, n-j) at 0.  The terms
+    r_j C(x, j), j >= 2, of the degree-1 window are bounded through the range
+    of U^(j) on the job's offsets plus the same dropped, shifted and
+    rounding parts of row j."""
+    d = delta
+    if not 1 <= d <= min(U.Du, 8):
+        raise ValueError("degree must be between 1 and the upper degree")
+    with mpmath.workprec(192):
+        c = U.coeffs
+        Du = U.Du
+        eps = mpf(2) ** (-U.s)
+        X = mpf(U.count + d * N + d)            # largest offset a difference reaches
+        fac = mpmath.factorial
+
+        def dmax(n):                            # max |U^(n)(x)|, 0 <= x <= X
+            return sum(abs(c[k]) * fac(k) / fac(k - n) * X ** (k - n) for k in range(n, Du + 1))
+
+        def drange(j):                          # range of U^(j) on [0, X]
+            lo = hi = c[j] * fac(j)
+            for k in range(j + 1, Du + 1):
+                term = c[k] * fac(k) / fac(k - j) * X ** (k - j)
+                lo += min(term, 0)
+                hi += max(term, 0)
+            return lo, hi
+
+        Mx = [dmax(n) for n in range(Du + 1)]
+        en = [U.shift_error(n) for n in range(Du + 1)]
+        drop = {}                               # |T[j][l]| of R_t, j + l > delta
+        keptE = {}                              # |Delta_N^l Delta_1^j E_t(0)|, j + l <= delta
+        for j in range(Du + 1):
+            for l in range(Du - j + 1):
+                if j + l > d:
+                    drop[(j, l)] = mpf(N) ** l * Mx[j + l]
+                else:
+                    keptE[(j, l)] = sum(en[n] * 2 ** l * comb(l * N, n - j)
+                                        for n in range(j + l, Du + 1))
+        e_drop = sum(v * comb(tau - 1, l) * comb(N - 1, j) for (j, l), v in drop.items())
+        e_shift = sum(v * comb(tau - 1, l) * comb(N - 1, j) for (j, l), v in keptE.items())
+        e_rw = round_bound(N, tau, d, W)
+        mu = U.e_approx + e_drop + e_shift + e_rw
+        t_lo = t_hi = mpf(0)
+        for j in range(2, d + 1):
+            lo_j, hi_j = drange(j)
+            slack = sum(drop[(j, l)] * comb(tau - 1, l) for l in range(d - j + 1, Du - j + 1)) \
+                + sum(keptE[(j, l)] * comb(tau - 1, l) for l in range(d - j + 1)) \
+                + mpf(2) ** (-W - 1) * sum(comb(tau - 1, l) for l in range(d - j + 1))
+            cj = comb(N - 1, j)
+            t_lo += min(lo_j - slack, 0) * cj
+            t_hi += max(hi_j + slack, 0) * cj
+        one = mpf(2) ** -64
+        lo = -(mu + t_hi + one)
+        width = 2 * eps + 2 * mu + (t_hi - t_lo) + (N + 1) * one
+        s64 = mpf(2) ** 64
+        win = np.array([int(mpmath.floor(lo * s64)) % M64,
+                        min(int(mpmath.ceil(width * s64)) + 2, M64 - 1)], np.uint64)
+        thr = np.array(value_bands(mu, eps), np.uint64)
+    return win, thr, mu

@@ -30,3 +30,21 @@ def read_golden(name):
 @pytest.fixture
 def golden():
     return read_golden
+
+
+def golden_hr_lists(name):
+    """HR-case lists of tests/golden/hr_<name>.txt (written by
+    tests/golden/make_lists.py from the oracle alone): {job id: sorted
+    offsets m}, or None when the file has not been generated."""
+    path = os.path.join(GOLDEN, f"hr_{name}.txt")
+    if not os.path.exists(path):
+        return None
+    out = {}
+    for line in read_golden(f"hr_{name}.txt"):
+        head, tail = line.split("|")
+        jid = int(head.split()[0])
+        lst = out.setdefault(jid, [])
+        m = tail.split()[0]
+        if m != "-":
+            lst.append(int(m))
+    return {j: sorted(v) for j, v in out.items()}

@@ -143,3 +143,20 @@ def test_each_parameter_check_returns_before_the_device():
     for kw in ({"group": 0}, {"n": 1 << 32}, {"win_d": None}, {"total": None},
                {"hits": None}, {"counts": None}):
         assert sch(**kw) == E, kw
+
+    def sub(du=7, wu=320, deg=4, width=256, max_t=4095, max_N=1 << 18, N=1 << 18, n_sub=1,
+            upper=p, out=p, t_idx=None, N_per=None, t0=0):
+        return L.hr_subtables(c, upper, du, wu, t_idx, t0, N_per, N, max_t, max_N, n_sub, deg,
+                              width, out, None)
+    assert sub() == DEV
+    for kw in ({"du": 0}, {"du": 11}, {"wu": 200}, {"wu": 512}, {"wu": 128}, {"deg": 0},
+               {"deg": 8}, {"width": 320}, {"width": 64}, {"du": 3, "deg": 4},
+               {"wu": 192, "width": 256}, {"max_t": (1 << 32) - 1},
+               {"max_N": 0}, {"max_N": (1 << 32) - 1, "N": 5, "du": 10},
+               {"N": 0}, {"N": (1 << 18) + 1}, {"t0": 4095, "n_sub": 2},
+               {"upper": None}, {"out": None}):
+        assert sub(**kw) == E, kw
+    assert sub(t_idx=p, t0=1 << 20, n_sub=2) == DEV     # t from the device array
+    assert sub(N_per=p, N=0) == DEV                     # N from the device array
+    assert sub(n_sub=0) == OK
+

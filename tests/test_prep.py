@@ -165,3 +165,77 @@ def test_value_bands_closed_forms():
                                     2 ** 64 - 2 ** 34 - 1]
     assert value_bands(mpf(2) ** -19, eps)[:2] == [2 ** 64 - 1, 0]
     assert value_bands(mpf(1) / 2, eps) == [2 ** 64 - 1, 0, 2 ** 64 - 1, 0]
+
+
+# ---------------------------------------------------------------- upper level
+
+@pytest.mark.parametrize("fname", ["exp", "exp2", "log", "sin", "cos"])
+@pytest.mark.parametrize("count,S,Du,Wu", [(1 << 36, 1 << 24, 6, 320), (1 << 20, 1 << 10, 4, 192)])
+def test_upper_table_equals_oracle(fname, count, S, Du, Wu):
+    """The product's upper table (fixed-point monomials through exact
+    integer matrices) equals the oracle's (Newton interpolation of mpmath
+    values on the grid, Sec. 5.1), word for word."""
+    from oracle.taylor import upper_table as oracle_upper
+    from paper_1211_3056_amd.prep import upper_table
+    U = upper_table(fname, STARTS[fname], count, 20, "rn", S, Du, Wu)
+    ref = oracle_upper(fname, STARTS[fname], count, 20, "rn", Du, S, Wu)
+    assert _ints(U.words, Wu) == [v for row in ref for v in row]
+
+
+@pytest.mark.parametrize("fname", ["exp", "exp2", "log", "sin", "cos"])
+@pytest.mark.parametrize("mode", ["rn", "dir"])
+def test_upper_windows_against_bruteforce(fname, mode):
+    """Sub-interval tables made from the upper table (by the oracle's
+    two-level shift, standing in for the device): every HR argument of each
+    piece is a candidate of the window upper_windows gives, and no value the
+    thresholds call certainly HR (or certainly not) contradicts the
+    per-argument brute force."""
+    from oracle.tabulate import subinterval_table
+    from paper_1211_3056_amd.prep import upper_table, upper_windows
+    N, tau, d, W, Du, Wu, T = 1 << 6, 1 << 4, 3, 128, 5, 192, 8
+    S = N * tau
+    count = S * T
+    job = Job(fname, STARTS[fname], count, 8, mode, N, tau, d, W)
+    cases = set(ohr.hr_bruteforce(job))
+    assert len(cases) > 20
+    U = upper_table(fname, STARTS[fname], count, 8, mode, S, Du, Wu)
+    win, thr, mu = upper_windows(U, N, tau, d, W)
+    assert mu < 2.0 ** -40
+    lo, width = int(win[0]), int(win[1])
+    hr_lo, hr_hi, rej_lo, rej_hi = (int(x) for x in thr)
+    Uw = _ints(U.words, Wu)
+    Urows = _rows_T(Uw, Du)
+    n_cand = 0
+    for t in range(T):
+        Tt = subinterval_table(Urows, Du, t, N, d, Wu, W)
+        for i in range(tau):
+            rows = straightforward_rows(Tt, d, i, W)
+            a, b = piece_ab(rows, W)
+            cand = set(brute_hits(a, b, N, width, lo=lo))
+            n_cand += len(cand)
+            base = t * S + i * N
+            for x in range(N):
+                m = base + x
+                tv = top64(evaluate(rows, x, W), W)
+                if m in cases:
+                    assert x in cand, m
+                    assert not (rej_lo <= tv <= rej_hi), m
+                elif hr_lo <= tv <= hr_hi:
+                    pytest.fail(f"value certain HR but brute force says no: {m}")
+    assert n_cand < count
+
+
+def test_upper_error_budget_shapes():
+    """At the large workload's shape (exp, 2^40 arguments, sub-intervals of
+    2^28, pieces of 2^18, degree 4 at 256 bits) a degree-7 upper polynomial
+    at 320 bits leaves an error below eps 2^-24 and a window within 0.1% of
+    the per-sub-interval Taylor windows; degree 6 is not enough for 2^-12."""
+    import mpmath
+    from paper_1211_3056_amd.prep import upper_table, upper_windows
+    U7 = upper_table("exp", 1.0, 1 << 40, 32, "rn", 1 << 28, 7, 320)
+    win, thr, mu = upper_windows(U7, 1 << 18, 1 << 10, 4, 256)
+    assert mu < mpmath.mpf(2) ** (-32 - 24)
+    P = prepare(JobSpec(**synth.CONFIG3), subs=[0, 4095])
+    assert int(P.win[:, 1].max()) <= int(win[1]) < int(P.win[:, 1].max()) * 1.001
+    U6 = upper_table("exp", 1.0, 1 << 40, 32, "rn", 1 << 28, 6, 320)
+    assert U6.e_approx > mpmath.mpf(2) ** (-32 - 12)
