@@ -57,7 +57,8 @@ typedef enum {
     HR_EINVAL = -1,      /* invalid argument; nothing launched            */
     HR_ECAPACITY = -2,   /* an output buffer was too small (see callers)  */
     HR_EDEVICE = -3,     /* HIP runtime or launch error                   */
-    HR_ENOMEM = -4       /* device scratch allocation failed              */
+    HR_ENOMEM = -4,      /* device scratch allocation failed              */
+    HR_ESCRATCH = -5     /* input larger than hr_search_static's scratch  */
 } hr_status;
 
 /* ABI version of the loaded library (HR_ABI_VERSION). */
@@ -104,6 +105,29 @@ hr_status hr_search(hr_ctx* ctx, const uint64_t* a, const uint64_t* b, const uin
                     uint64_t n, const uint64_t* win_lo, const uint64_t* win_d, uint32_t group,
                     uint32_t* counts, uint64_t* offsets, uint32_t* hits, uint32_t* hit_inst,
                     uint64_t cap, uint64_t* total, void* stream);
+
+/*
+ * hr_search_static -- hr_search for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same arguments, results and errors, but the block
+ * sums live in a fixed device array of the library (HR_STATIC_SCRATCH_BYTES
+ * per device, held until the process ends) instead of the context's
+ * growable scratch, and the call allocates nothing.
+ *  - n is limited to HR_STATIC_MAX_INSTANCES; larger n returns HR_ESCRATCH
+ *    before any launch.
+ *  - Every call on a device shares that device's array: calls that overlap
+ *    on one device (other streams, other contexts, other host threads) race
+ *    and give wrong results.  Order them on one stream.
+ *  - Nothing in the array needs clearing between calls: every word a call
+ *    reads is written earlier in the same call.
+ */
+#define HR_STATIC_SCRATCH_BYTES (1u << 20)
+#define HR_STATIC_MAX_INSTANCES ((uint64_t)((HR_STATIC_SCRATCH_BYTES / 8) - 1) * 256)
+hr_status hr_search_static(hr_ctx* ctx, const uint64_t* a, const uint64_t* b,
+                           const uint32_t* N, uint64_t n, const uint64_t* win_lo,
+                           const uint64_t* win_d, uint32_t group, uint32_t* counts,
+                           uint64_t* offsets, uint32_t* hits, uint32_t* hit_inst, uint64_t cap,
+                           uint64_t* total, void* stream);
 
 /*
  * hr_tabulate -- tabulation of degree-1 pieces (Sec. 5 of the paper:

@@ -16,7 +16,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhrsearch.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "hrsearch.h")
 
-HR_OK, HR_EINVAL, HR_ECAPACITY, HR_EDEVICE, HR_ENOMEM = 0, -1, -2, -3, -4
+HR_OK, HR_EINVAL, HR_ECAPACITY, HR_EDEVICE, HR_ENOMEM, HR_ESCRATCH = 0, -1, -2, -3, -4, -5
+HR_STATIC_MAX_INSTANCES = ((1 << 20) // 8 - 1) * 256
 HR_WAVES_FILL = 0xFFFFFFFF
 
 _lib = None
@@ -44,7 +45,8 @@ class hr_item(ctypes.Structure):
 RESULT_BYTES = ctypes.sizeof(hr_result)
 ITEM_BYTES = ctypes.sizeof(hr_item)
 EXPORTS = ("hr_abi_version", "hr_status_str", "hr_create", "hr_destroy", "hr_search", "hr_batch_run",
-           "hr_tabulate", "hr_recheck", "hr_pipeline", "hr_quot_check", "hr_subtables")
+           "hr_tabulate", "hr_recheck", "hr_pipeline", "hr_quot_check", "hr_subtables",
+           "hr_search_static")
 
 
 def lib():
@@ -66,6 +68,8 @@ def lib():
     L.hr_destroy.argtypes = [P]
     L.hr_search.restype = i32
     L.hr_search.argtypes = [P, P, P, P, u64, P, P, u32, P, P, P, P, u64, P, P]
+    L.hr_search_static.restype = i32
+    L.hr_search_static.argtypes = [P, P, P, P, u64, P, P, u32, P, P, P, P, u64, P, P]
     L.hr_tabulate.restype = i32
     L.hr_tabulate.argtypes = [P, P, u32, u32, u32, u32, P, P, P]
     L.hr_recheck.restype = i32
@@ -133,6 +137,13 @@ def hr_search(ctx, a, b, N, win_lo, win_d, group, counts, offsets, hits, hit_ins
     _check("hr_search", lib().hr_search(ctx.handle, _p(a), _p(b), _p(N), a.numel(), _p(win_lo),
                                         _p(win_d), group, _p(counts), _p(offsets), _p(hits),
                                         _p(hit_inst), cap, _p(total), _stream(stream)))
+
+
+def hr_search_static(ctx, a, b, N, win_lo, win_d, group, counts, offsets, hits, hit_inst, cap,
+                     total, stream=None):
+    _check("hr_search_static", lib().hr_search_static(
+        ctx.handle, _p(a), _p(b), _p(N), a.numel(), _p(win_lo), _p(win_d), group, _p(counts),
+        _p(offsets), _p(hits), _p(hit_inst), cap, _p(total), _stream(stream)))
 
 
 def hr_tabulate(ctx, table, n_sub, degree, tau, width, a_out, b_out, stream=None):

@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <mutex>
 
 #include <stdint.h>
 #include <stdlib.h>
@@ -34,6 +35,15 @@ struct hr_ctx {
                             // captured graph may keep pointing at it): the
                             // work-claim counter, then the statistics slots
 };
+
+// Device scratch of hr_search_static: the per-block hit counts of the
+// search and their scan (one uint64 per 256-instance block, plus one), in a
+// fixed file-scope array instead of memory allocated by the library, for
+// callers that cannot allocate.  Each device holds its own copy for the
+// life of the process; host code uses only the address that
+// hipGetSymbolAddress returns for the current device, never this name.
+constexpr uint64_t kStaticScratchWords = 1ull << 17;   // 1 MiB
+static __device__ __align__(256) uint64_t scratch[kStaticScratchWords];
 
 namespace {
 
@@ -1098,6 +1108,25 @@ uint32_t resident_waves(int device) {
     return w;
 }
 
+// Device address of `scratch` on each device, looked up once per device
+// (by hr_create, with that device current) and kept for the process.
+std::mutex g_static_mu;
+uint64_t* g_static_addr[64];
+
+hr_status static_scratch(int device, uint64_t** out) {
+    if (device < 0 || device >= 64) return HR_EINVAL;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_addr[device]) {
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess || cur != device) return HR_EDEVICE;
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return HR_EDEVICE;
+        g_static_addr[device] = (uint64_t*)p;
+    }
+    *out = g_static_addr[device];
+    return HR_OK;
+}
+
 hr_status ensure_scratch(hr_ctx* ctx, size_t bytes) {
     if (ctx->scratch_bytes >= bytes) return HR_OK;
     if (ctx->scratch) {
@@ -1191,6 +1220,7 @@ const char* hr_status_str(int s) {
         case HR_ECAPACITY: return "output capacity exceeded";
         case HR_EDEVICE: return "HIP device or launch error";
         case HR_ENOMEM: return "device allocation failed";
+        case HR_ESCRATCH: return "input larger than the static scratch allows";
         default: return "unknown status";
     }
 }
@@ -1205,6 +1235,11 @@ hr_status hr_create(hr_ctx** out, int device) {
     hr_ctx* c = (hr_ctx*)calloc(1, sizeof(hr_ctx));
     if (!c) return HR_ENOMEM;
     c->device = device;
+    uint64_t* st_addr = nullptr;
+    if (static_scratch(device, &st_addr) != HR_OK) {
+        free(c);
+        return HR_EDEVICE;
+    }
     if (hipMalloc(&c->fixed, kFixedBytes) != hipSuccess) {
         free(c);
         return HR_ENOMEM;
@@ -1229,20 +1264,27 @@ hr_status hr_destroy(hr_ctx* ctx) {
     return HR_OK;
 }
 
-hr_status hr_search(hr_ctx* ctx, const uint64_t* a, const uint64_t* b, const uint32_t* N,
-                    uint64_t n, const uint64_t* win_lo, const uint64_t* win_d, uint32_t group,
-                    uint32_t* counts, uint64_t* offsets, uint32_t* hits, uint32_t* hit_inst,
-                    uint64_t cap, uint64_t* total, void* stream) {
+}  // extern "C"
+
+namespace {
+
+hr_status search_args_ok(hr_ctx* ctx, const uint64_t* a, const uint64_t* b, const uint32_t* N,
+                         uint64_t n, const uint64_t* win_d, uint32_t group, uint32_t* counts,
+                         uint64_t* offsets, uint32_t* hits, uint64_t cap, uint64_t* total) {
     if (!ctx || !win_d || !total || group == 0) return HR_EINVAL;
     if (n > 0xffffffffull) return HR_EINVAL;
     if (n > 0 && (!a || !b || !N || !counts || !offsets)) return HR_EINVAL;
     if (cap > 0 && !hits) return HR_EINVAL;
-    if (hipSetDevice(ctx->device) != hipSuccess) return HR_EDEVICE;
-    hipStream_t st = as_stream(stream);
+    return HR_OK;
+}
+
+// The search's three launches, with the block sums in bsum (nb + 1 words).
+hr_status search_launch(const uint64_t* a, const uint64_t* b, const uint32_t* N, uint64_t n,
+                        const uint64_t* win_lo, const uint64_t* win_d, uint32_t group,
+                        uint32_t* counts, uint64_t* offsets, uint32_t* hits, uint32_t* hit_inst,
+                        uint64_t cap, uint64_t* total, uint64_t* bsum, hipStream_t st) {
     const uint64_t nb = (n + kBlock - 1) / kBlock;
-    hr_status s = ensure_scratch(ctx, (nb + 1) * sizeof(uint64_t));
-    if (s != HR_OK) return s;
-    uint64_t* bsum = (uint64_t*)ctx->scratch;
+    hr_status s = HR_OK;
     if (nb > 0) {
         k_search_count<<<dim3((uint32_t)nb), dim3(kBlock), 0, st>>>(a, b, N, n, win_lo, win_d,
                                                                     group, counts, bsum);
@@ -1256,6 +1298,39 @@ hr_status hr_search(hr_ctx* ctx, const uint64_t* a, const uint64_t* b, const uin
         if ((s = launched()) != HR_OK) return s;
     }
     return HR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hr_status hr_search(hr_ctx* ctx, const uint64_t* a, const uint64_t* b, const uint32_t* N,
+                    uint64_t n, const uint64_t* win_lo, const uint64_t* win_d, uint32_t group,
+                    uint32_t* counts, uint64_t* offsets, uint32_t* hits, uint32_t* hit_inst,
+                    uint64_t cap, uint64_t* total, void* stream) {
+    hr_status s = search_args_ok(ctx, a, b, N, n, win_d, group, counts, offsets, hits, cap, total);
+    if (s != HR_OK) return s;
+    if (hipSetDevice(ctx->device) != hipSuccess) return HR_EDEVICE;
+    const uint64_t nb = (n + kBlock - 1) / kBlock;
+    if ((s = ensure_scratch(ctx, (nb + 1) * sizeof(uint64_t))) != HR_OK) return s;
+    return search_launch(a, b, N, n, win_lo, win_d, group, counts, offsets, hits, hit_inst, cap,
+                         total, (uint64_t*)ctx->scratch, as_stream(stream));
+}
+
+hr_status hr_search_static(hr_ctx* ctx, const uint64_t* a, const uint64_t* b,
+                           const uint32_t* N, uint64_t n, const uint64_t* win_lo,
+                           const uint64_t* win_d, uint32_t group, uint32_t* counts,
+                           uint64_t* offsets, uint32_t* hits, uint32_t* hit_inst, uint64_t cap,
+                           uint64_t* total, void* stream) {
+    hr_status s = search_args_ok(ctx, a, b, N, n, win_d, group, counts, offsets, hits, cap, total);
+    if (s != HR_OK) return s;
+    const uint64_t nb = (n + kBlock - 1) / kBlock;
+    if (nb + 1 > kStaticScratchWords) return HR_ESCRATCH;
+    if (hipSetDevice(ctx->device) != hipSuccess) return HR_EDEVICE;
+    uint64_t* bsum = nullptr;
+    if ((s = static_scratch(ctx->device, &bsum)) != HR_OK) return s;
+    return search_launch(a, b, N, n, win_lo, win_d, group, counts, offsets, hits, hit_inst, cap,
+                         total, bsum, as_stream(stream));
 }
 
 hr_status hr_tabulate(hr_ctx* ctx, const uint64_t* table, uint32_t n_sub, uint32_t degree,

@@ -75,7 +75,10 @@ def test_header_constants_match_binding():
     codes = dict(re.findall(r"\b(HR_E[A-Z]+|HR_OK)\s*=\s*(-?\d+)", text))
     assert {k: int(v) for k, v in codes.items()} == {
         "HR_OK": _lib.HR_OK, "HR_EINVAL": _lib.HR_EINVAL, "HR_ECAPACITY": _lib.HR_ECAPACITY,
-        "HR_EDEVICE": _lib.HR_EDEVICE, "HR_ENOMEM": _lib.HR_ENOMEM}
+        "HR_EDEVICE": _lib.HR_EDEVICE, "HR_ENOMEM": _lib.HR_ENOMEM,
+        "HR_ESCRATCH": _lib.HR_ESCRATCH}
+    sbytes = int(re.search(r"#define HR_STATIC_SCRATCH_BYTES \(1u << (\d+)\)", text).group(1))
+    assert _lib.HR_STATIC_MAX_INSTANCES == ((1 << sbytes) // 8 - 1) * 256
 
 
 def _gpu_visible():
@@ -160,3 +163,12 @@ def test_each_parameter_check_returns_before_the_device():
     assert sub(N_per=p, N=0) == DEV                     # N from the device array
     assert sub(n_sub=0) == OK
 
+    def sst(n=1, group=1, win_d=p, total=p, hits=p, cap=1, counts=p):
+        return L.hr_search_static(c, p, p, p, n, p, win_d, group, counts, p, hits, p, cap, total,
+                                  None)
+    assert sst() == DEV
+    for kw in ({"group": 0}, {"n": 1 << 32}, {"win_d": None}, {"total": None},
+               {"hits": None}, {"counts": None}):
+        assert sst(**kw) == E, kw
+    assert sst(n=_lib.HR_STATIC_MAX_INSTANCES + 1) == _lib.HR_ESCRATCH
+    assert sst(n=_lib.HR_STATIC_MAX_INSTANCES) == DEV
