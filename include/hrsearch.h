@@ -296,6 +296,17 @@ hr_status hr_subtables(hr_ctx* ctx, const uint64_t* upper, uint32_t upper_degree
                        void* stream);
 
 /*
+ * hr_search_steps -- diagnostic: steps[i] = number of partial quotients the
+ * closest-point walk of hr_search computes for instance i (arguments as
+ * hr_search; 0 where N[i] = 0, the window is empty, a = 0 or N[i] = 1).
+ * For measuring the search's algorithmic work.  steps: uint32[n] (device).
+ * Errors: HR_EINVAL for n > 2^32 - 1, group == 0 or a null pointer.
+ */
+hr_status hr_search_steps(hr_ctx* ctx, const uint64_t* a, const uint64_t* b, const uint32_t* N,
+                          uint64_t n, const uint64_t* win_lo, const uint64_t* win_d,
+                          uint32_t group, uint32_t* steps, void* stream);
+
+/*
  * hr_quot_check -- diagnostic: the partial-quotient routine of the search,
  * out[i] = min(floor(num[i] / den[i]), cap) computed by the device code
  * (binary64 reciprocal estimate + exact correction); out[i] = 2^64 - 1 where

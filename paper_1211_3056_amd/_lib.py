@@ -46,7 +46,7 @@ RESULT_BYTES = ctypes.sizeof(hr_result)
 ITEM_BYTES = ctypes.sizeof(hr_item)
 EXPORTS = ("hr_abi_version", "hr_status_str", "hr_create", "hr_destroy", "hr_search", "hr_batch_run",
            "hr_tabulate", "hr_recheck", "hr_pipeline", "hr_quot_check", "hr_subtables",
-           "hr_search_static")
+           "hr_search_static", "hr_search_steps")
 
 
 def lib():
@@ -70,6 +70,8 @@ def lib():
     L.hr_search.argtypes = [P, P, P, P, u64, P, P, u32, P, P, P, P, u64, P, P]
     L.hr_search_static.restype = i32
     L.hr_search_static.argtypes = [P, P, P, P, u64, P, P, u32, P, P, P, P, u64, P, P]
+    L.hr_search_steps.restype = i32
+    L.hr_search_steps.argtypes = [P, P, P, P, u64, P, P, u32, P, P]
     L.hr_tabulate.restype = i32
     L.hr_tabulate.argtypes = [P, P, u32, u32, u32, u32, P, P, P]
     L.hr_recheck.restype = i32
@@ -144,6 +146,12 @@ def hr_search_static(ctx, a, b, N, win_lo, win_d, group, counts, offsets, hits, 
     _check("hr_search_static", lib().hr_search_static(
         ctx.handle, _p(a), _p(b), _p(N), a.numel(), _p(win_lo), _p(win_d), group, _p(counts),
         _p(offsets), _p(hits), _p(hit_inst), cap, _p(total), _stream(stream)))
+
+
+def hr_search_steps(ctx, a, b, N, win_lo, win_d, group, steps, stream=None):
+    _check("hr_search_steps", lib().hr_search_steps(ctx.handle, _p(a), _p(b), _p(N), a.numel(),
+                                                    _p(win_lo), _p(win_d), group, _p(steps),
+                                                    _stream(stream)))
 
 
 def hr_tabulate(ctx, table, n_sub, degree, tau, width, a_out, b_out, stream=None):

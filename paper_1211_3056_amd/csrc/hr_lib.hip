@@ -2,12 +2,15 @@
 //
 // Kernels
 //   k_search_count / k_scan_blocks / k_search_emit   degree-1 search, CSR out
+//   k_subtables                                      sub-interval tables from
+//                                                    a range's upper table
 //   k_tabulate                                       pieces (a, b)
 //   k_recheck                                        exact candidate values
 //   k_pipeline                                       fused tabulate+search+recheck
 //   k_items                                          the same over work items
 //                                                    (batched, persistent)
-//   k_zero_u32, k_stats_flush, k_quot_check          counters, diagnostics
+//   k_zero_u32, k_stats_flush                        counters
+//   k_search_steps, k_quot_check                     diagnostics
 //
 // Every kernel maps one lane to one independent unit of work (an instance,
 // a set of pieces, a candidate): the search is embarrassingly parallel over
@@ -16,6 +19,7 @@
 // quotient estimates.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <mutex>
 
@@ -233,78 +237,6 @@ __device__ __forceinline__ void row_step(hr::Word<L>* v) {
 
 constexpr uint32_t kMaxNu = 16;   // pieces per lane (pick_nu never exceeds it)
 
-// One wave: lane l expands its packet of cnt <= nu consecutive pieces.  The
-// outputs of a wave's lanes form one contiguous range of the flattened
-// (sub-interval, piece) order (a lane is followed by the next packet of its
-// sub-interval, or by the first packet of the next one), so the pieces are
-// staged in LDS and written back as runs of consecutive pieces rather than
-// as 64 strided streams.  The staging holds kPart pieces per lane at a time
-// (slot = lane kPart + s, at LDS index slot + slot / kPart: one pad entry
-// per lane keeps the lanes' staging writes on distinct banks), so a packet
-// of nu pieces goes out in ceil(nu / kPart) parts; half a packet's worth of
-// LDS per wave leaves room for more resident waves per CU.  Where L x DEG
-// <= 32 (L 32-bit limbs per word: W = 256 with degree 4, or less) the
-// kernel is held to 128 VGPRs, 4 waves per SIMD (a few bytes of scratch at
-// W = 256, degree 4), so a grid of one wave per sub-interval fits the
-// device in one round.
-constexpr uint32_t kPart = kMaxNu / 2;
-template <int L, int DEG>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(L * DEG <= 32 ? 4 : 1)))
-void k_tabulate(const uint64_t* __restrict__ table, uint32_t n_sub, uint32_t tau, uint32_t nu,
-                uint64_t* __restrict__ a_out, uint64_t* __restrict__ b_out) {
-    constexpr uint32_t kStage = 64 * kPart + 64;
-    __shared__ uint64_t s_a[kStage];
-    __shared__ uint64_t s_b[kStage];
-    __shared__ uint32_t s_e0[64];
-    __shared__ uint32_t s_cnt[64];
-    const int lane = threadIdx.x;
-    const uint64_t gid = (uint64_t)blockIdx.x * 64 + lane;
-    const uint64_t per_sub = (tau + nu - 1) / nu;
-    const bool active = gid < (uint64_t)n_sub * per_sub;   // lane 0 always is
-    uint64_t sub = 0, i0 = 0, base = 0;
-    uint32_t cnt = 0;
-    if (active) {
-        sub = gid / per_sub;
-        i0 = (gid % per_sub) * nu;
-        cnt = (uint32_t)hr::umin(nu, tau - i0);
-        base = sub * tau + i0;
-    }
-    const uint64_t wbase = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(base >> 32)) << 32) |
-                           (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)base);
-    s_e0[lane] = (uint32_t)(base - wbase);   // offset of the lane's packet in the range
-    s_cnt[lane] = cnt;                         // 0 for inactive lanes
-    hr::Word<L> v0[DEG + 1], v1[DEG];
-    if (active) {
-        const uint64_t* T = table + sub * n_entries(DEG) * (L / 2);
-        uint32_t cb[DEG][4];
-        binom_limbs<DEG>(i0, cb);
-        row_start<L, DEG, 0>(T, cb, v0);
-        row_start<L, DEG, 1>(T, cb, v1);
-    }
-    for (uint32_t p0 = 0; p0 < nu; p0 += kPart) {   // uniform: nu is a kernel argument
-        if (active) {
-            const uint32_t end = (uint32_t)hr::umin(cnt, p0 + kPart);
-            for (uint32_t s = p0; s < end; ++s) {
-                const uint32_t slot = (uint32_t)lane * kPart + (s - p0);
-                s_b[slot + slot / kPart] = top64(v0[0]);
-                s_a[slot + slot / kPart] = neg_top64(v1[0]);
-                row_step<L, DEG + 1>(v0);
-                row_step<L, DEG>(v1);
-            }
-        }
-        __syncthreads();
-        for (uint32_t slot = lane; slot < 64 * kPart; slot += 64) {
-            const uint32_t src = slot / kPart, s = p0 + slot % kPart;
-            if (s < s_cnt[src]) {
-                const uint64_t e = wbase + s_e0[src] + s;
-                b_out[e] = s_b[slot + slot / kPart];
-                a_out[e] = s_a[slot + slot / kPart];
-            }
-        }
-        __syncthreads();
-    }
-}
-
 // ---------------------------------------------------------------- sub-interval tables
 
 // w *= x mod 2^(32 L) for a 64-bit x.
@@ -317,18 +249,25 @@ __device__ __forceinline__ void wmul_u64(hr::Word<L>& w, uint64_t x) {
     w = acc;
 }
 
-// w /= k for a w that k divides (k < 2^16): long division from the top
-// limb.  Each partial dividend r 2^32 + limb is below 2^48, so its binary64
-// quotient by k is exact enough that the floor is the integer quotient
-// (the fractional part is a multiple of 1/k, far from 1 - 2^-53 relative).
+// w /= k for a w that k divides (k <= 64): long division from the top
+// limb.  Each partial dividend c = r 2^32 + limb is below 2^38; its product
+// with the binary64 reciprocal of k is within 2^-14 of c / k, whose
+// fractional part is a multiple of 1/k, so the floor is the quotient or one
+// below it (when c / k is an integer just above the rounded product); one
+// compare of the remainder finishes it.
 template <int L>
 __device__ __forceinline__ void wdiv_exact(hr::Word<L>& w, uint32_t k) {
+    const double rk = 1.0 / (double)k;
     uint64_t r = 0;
 #pragma unroll
     for (int i = L - 1; i >= 0; --i) {
-        const uint64_t cur = (r << 32) | w.w[i];
-        const uint64_t q = hr::idx_div(cur, k);
-        r = cur - q * k;
+        const uint64_t c = (r << 32) | w.w[i];
+        uint64_t q = (uint64_t)__builtin_floor(hr::u64_to_f64(c) * rk);
+        uint64_t rem = c - q * k;
+        const bool up = rem >= k;
+        q += up;
+        rem -= up ? k : 0;
+        r = rem;
         w.w[i] = (uint32_t)q;
     }
 }
@@ -345,91 +284,120 @@ __device__ __forceinline__ void wsub(hr::Word<L>& acc, const hr::Word<L>& x) {
     }
 }
 
-constexpr int kMaxUpperDegree = HR_MAX_UPPER_DEGREE;
+template <int L>
+__device__ __forceinline__ void lds_get(const uint32_t* p, hr::Word<L>& w) {
+#pragma unroll
+    for (int i = 0; i < L; ++i) w.w[i] = p[i];
+}
 
-// One lane per (output table i, entry (j, l)) of the sub-interval tables
-// made from an upper table U of degree du (steps 1 and S, LU 32-bit limbs
-// per word).  With R_t(y) = U(t S + y) held by its step-1 differences
-// D[n] = Delta_1^n R_t(0) = sum_m U[n][m] C(t, m) (straightforward shift in
-// the sub-interval index, Sec. 5.2), the entry is
-//   T[j][l] = Delta_N^l Delta_1^j R_t(0)
-//           = sum_s (-1)^(l-s) C(l, s) r_j(s N),  r_j(y) = sum_k C(y, k) D[j+k],
-// exact mod 2^(32 LU), then rounded to the nearest W-bit word.  C(t, m) is
-// an exact 128-bit integer (t^du < 2^128) and C(s N, k) an exact LU-limb
-// integer ((deg N)^du < 2^(32 LU)); both are built one step at a time,
-// C(y, k) = C(y, k-1) (y - k + 1) / k.
+template <int L>
+__device__ __forceinline__ void lds_put(uint32_t* p, const hr::Word<L>& w) {
+#pragma unroll
+    for (int i = 0; i < L; ++i) p[i] = w.w[i];
+}
+
+constexpr int kMaxUpperDegree = HR_MAX_UPPER_DEGREE;
+// LDS words (of LU limbs) per wave: every lane group's binomial table
+// (deg + 1)(du + 1) words and its D vector (du + 1 words).
+constexpr int kSubtabWords = 4 * 66;
+
+// Sub-interval tables made from an upper table U of degree du (steps 1 and
+// S, LU 32-bit limbs per word).  A group of G lanes (G = 16, 32 or 64, at
+// least the table's entries and deg + du + 2) makes one sub-interval's
+// table; with R_t(y) = U(t S + y) and N its piece length:
+//   phase 1  lanes s <= deg: the exact integers C(s N, k), k <= du, built
+//            one factor at a time, C(y, k) = C(y, k-1) (y - k + 1) / k;
+//            lanes deg + 1 + n, n <= du: D[n] = Delta_1^n R_t(0) =
+//            sum_m U[n][m] C(t, m) (straightforward shift in the sub-interval
+//            index, Sec. 5.2; C(t, m) exact in 128 bits);
+//   phase 2  lane k <= du: the l-th differences over s of C(s N, k) in
+//            place, A[l][k] = sum_s (-1)^(l-s) C(l, s) C(s N, k), the
+//            coefficient of Delta_1^k in Delta_N^l = (E^N - 1)^l;
+//   phase 3  lane e < E, entry (j, l): T[j][l] = Delta_N^l Delta_1^j R_t(0)
+//            = sum_{k=l}^{du-j} A[l][k] D[j+k] mod 2^(32 LU), rounded to the
+//            nearest W-bit word and written.
+// Exactness of the integer steps needs (deg N)^du < 2^(32 LU) and
+// t^du < 2^128 (checked on the host through max_N and max_t).
 template <int LU>
 __global__ __launch_bounds__(64) void k_subtables(
     const uint64_t* __restrict__ upper, uint32_t du, const uint32_t* __restrict__ t_idx,
     uint32_t t0, const uint32_t* __restrict__ N_per, uint32_t N0, uint32_t max_t, uint32_t max_N,
-    uint32_t n_sub, uint32_t deg, uint32_t wbits, uint64_t* __restrict__ out) {
-    const uint32_t E = (deg + 1) * (deg + 2) / 2;
-    const uint64_t g = (uint64_t)blockIdx.x * 64 + threadIdx.x;
-    const uint64_t i = g / E;
-    if (i >= n_sub) return;
-    uint32_t e = (uint32_t)(g % E);
-    const uint32_t e_out = e;
-    uint32_t j = 0;
-    while (e > deg - j) {   // entry e of the (j, l) order
-        e -= deg - j + 1;
-        ++j;
-    }
-    const uint32_t l = e;
-    const uint32_t lw = wbits / 64;
-    uint64_t* dst = out + (i * E + e_out) * lw;
-    const uint32_t t = t_idx ? t_idx[i] : t0 + (uint32_t)i;
-    const uint32_t N = N_per ? N_per[i] : N0;
-    if (t > max_t || N == 0 || N > max_N) {
-        for (uint32_t w = 0; w < lw; ++w) dst[w] = 0;
-        return;
-    }
+    uint32_t n_sub, uint32_t deg, uint32_t wbits, uint32_t G, uint64_t* __restrict__ out) {
+    __shared__ uint32_t lds[kSubtabWords * LU];
     constexpr int LW = LU / 2;   // 64-bit limbs of an upper word
-    // D[j .. du] (only those entry (j, l) reads: D[j + k], k <= du - j)
-    hr::Word<LU> D[kMaxUpperDegree + 1];
-#pragma unroll
-    for (int k = 0; k <= kMaxUpperDegree; ++k) {
-        if (k > (int)(du - j)) break;
-        const uint32_t n = j + k;
+    const uint32_t lane = threadIdx.x;
+    const uint32_t grp = lane / G, g = lane % G;
+    const uint64_t i = (uint64_t)blockIdx.x * (64 / G) + grp;
+    const bool valid_i = i < n_sub;
+    const uint32_t E = (deg + 1) * (deg + 2) / 2;
+    const uint32_t t = valid_i ? (t_idx ? t_idx[i] : t0 + (uint32_t)i) : 0;
+    const uint32_t N = valid_i ? (N_per ? N_per[i] : N0) : 1;
+    const bool ok = valid_i && t <= max_t && N != 0 && N <= max_N;
+    const uint32_t stride_w = (deg + 1) * (du + 1) + du + 1;
+    uint32_t* cs = lds + (size_t)grp * stride_w * LU;       // cs[s (du+1) + k]
+    uint32_t* Dl = cs + (size_t)(deg + 1) * (du + 1) * LU;  // D[n]
+    // phase 1
+    if (ok && g <= deg) {
+        const uint64_t y = (uint64_t)g * N;
+        hr::Word<LU> c;
+        hr::wzero(c);
+        c.w[0] = 1;
+        lds_put<LU>(cs + (size_t)(g * (du + 1)) * LU, c);
+        for (uint32_t k = 1; k <= du; ++k) {
+            wmul_u64<LU>(c, y - (uint64_t)(k - 1));   // wraps to 0 past y: C(y, k) = 0
+            wdiv_exact<LU>(c, k);
+            lds_put<LU>(cs + (size_t)(g * (du + 1) + k) * LU, c);
+        }
+    } else if (ok && g >= deg + 1 && g <= deg + 1 + du) {
+        const uint32_t n = g - deg - 1;
         hr::Word<LU> acc;
         load_word<LU>(upper + (size_t)entry(du, n, 0) * LW, acc);
         hr::Word<4> c;             // C(t, m), exact
         hr::wzero(c);
         c.w[0] = 1;
-#pragma unroll
-        for (int m = 1; m <= kMaxUpperDegree; ++m) {
-            if (m > (int)(du - n)) break;
+        for (uint32_t m = 1; m + n <= du; ++m) {
             wmul_u64<4>(c, (uint64_t)t - (uint64_t)(m - 1));
-            wdiv_exact<4>(c, (uint32_t)m);
+            wdiv_exact<4>(c, m);
             hr::Word<LU> u;
             load_word<LU>(upper + (size_t)entry(du, n, m) * LW, u);
             hr::wmac128(acc, u, c.w);
         }
-        D[k] = acc;
+        lds_put<LU>(Dl + (size_t)n * LU, acc);
     }
-    // T[j][l] = sum_s (-1)^(l-s) C(l, s) r_j(s N)
+    __syncthreads();
+    // phase 2: in-place forward differences over s, column k = g
+    if (ok && g <= du) {
+        for (uint32_t r = 1; r <= deg; ++r)
+            for (uint32_t s = deg; s >= r; --s) {
+                hr::Word<LU> hi, lo;
+                lds_get<LU>(cs + (size_t)(s * (du + 1) + g) * LU, hi);
+                lds_get<LU>(cs + (size_t)((s - 1) * (du + 1) + g) * LU, lo);
+                wsub<LU>(hi, lo);
+                lds_put<LU>(cs + (size_t)(s * (du + 1) + g) * LU, hi);
+            }
+    }
+    __syncthreads();
+    // phase 3
+    if (!valid_i || g >= E) return;
+    uint32_t e = g, j = 0;
+    while (e > deg - j) {   // entry g of the (j, l) order
+        e -= deg - j + 1;
+        ++j;
+    }
+    const uint32_t l = e;
+    const uint32_t lw = wbits / 64;
+    uint64_t* dst = out + (i * E + g) * lw;
+    if (!ok) {
+        for (uint32_t w = 0; w < lw; ++w) dst[w] = 0;
+        return;
+    }
     hr::Word<LU> T;
     hr::wzero(T);
-    uint32_t cls = 1;   // C(l, s)
-    for (uint32_t s = 0; s <= l; ++s) {
-        if (s > 0) cls = cls * (l - s + 1) / s;
-        const uint64_t y = (uint64_t)s * N;
-        hr::Word<LU> r = D[0];
-        hr::Word<LU> c;            // C(y, k), exact
-        hr::wzero(c);
-        c.w[0] = 1;
-#pragma unroll
-        for (int k = 1; k <= kMaxUpperDegree; ++k) {
-            if (k > (int)(du - j)) break;
-            wmul_u64<LU>(c, y - (uint64_t)(k - 1));
-            wdiv_exact<LU>(c, (uint32_t)k);
-            hr::wmac_n<LU, LU>(r, D[k], c.w);
-        }
-        hr::Word<LU> rc;
-        hr::wzero(rc);
-        const uint32_t m1[1] = {cls};
-        hr::wmac_n<LU, 1>(rc, r, m1);
-        if ((l - s) & 1) wsub(T, rc);
-        else hr::wadd(T, rc);
+    for (uint32_t k = l; k + j <= du; ++k) {
+        hr::Word<LU> a, d;
+        lds_get<LU>(cs + (size_t)(l * (du + 1) + k) * LU, a);
+        lds_get<LU>(Dl + (size_t)(j + k) * LU, d);
+        hr::wmac_n<LU, LU>(T, d, a.w);
     }
     // round to the nearest W-bit word (ties upwards), keep its W bits
     const uint32_t drop = 32 * LU - wbits;   // bits below the kept word
@@ -885,6 +853,70 @@ __device__ __forceinline__ void start_low(const uint64_t* __restrict__ T, uint64
     scale_top<L, DEG>(s_top);
 }
 
+// ---------------------------------------------------------------- tabulate
+
+// A whole step-1 difference vector v[0..LEN) of a polynomial of degree
+// LEN - 1 -> its differences with step kStride, in place (entry m reads
+// only entries >= m).  Multipliers below 2^32 take one-limb products.
+template <int L, int LEN>
+__device__ __forceinline__ void row_full_to_stride(hr::Word<L>* v) {
+    static_for<1, LEN>([&](auto M) {
+        constexpr int m = decltype(M)::value;
+        hr::Word<L> acc;
+        hr::wzero(acc);
+        static_for<m, LEN>([&](auto K) {
+            constexpr int k = decltype(K)::value;
+            constexpr uint64_t c = kStrideCoef.a[m][k];
+            if constexpr (c < (1ull << 32)) {
+                const uint32_t m1[1] = {(uint32_t)c};
+                hr::wmac_n<L, 1>(acc, v[k], m1);
+            } else {
+                wmac64<L>(acc, v[k], c);
+            }
+        });
+        v[m] = acc;
+    });
+}
+
+// One wave: a range of 64 nu consecutive pieces of one sub-interval, lane
+// l taking pieces l, l + 64, .., l + 64 (nu - 1) of it.  Each lane starts
+// from the step-1 difference vectors of rows 0 and 1 at its first piece
+// (straightforward shift, Sec. 5.2), turns them into differences with step
+// 64 (the same conversion as the fused pass), and then advances by one
+// tabulated-difference step per piece (Fig. 7).  At every step the 64 lanes
+// hold 64 consecutive pieces, so each a[] and b[] store of the wave is one
+// contiguous, line-aligned 512-byte run: no staging, no barrier, and no
+// partial cache lines.
+template <int L, int DEG>
+__global__ __launch_bounds__(64) void k_tabulate(const uint64_t* __restrict__ table,
+                                                 uint32_t tau, uint32_t nu, uint32_t wps,
+                                                 uint64_t* __restrict__ a_out,
+                                                 uint64_t* __restrict__ b_out) {
+    const int lane = threadIdx.x;
+    const uint64_t sub = blockIdx.x / wps;
+    const uint64_t i0 = (uint64_t)(blockIdx.x % wps) * kStride * nu + lane;
+    if (i0 >= tau) return;
+    const uint32_t cnt = (uint32_t)hr::umin(nu, (tau - i0 + kStride - 1) / kStride);
+    const uint64_t* T = table + sub * n_entries(DEG) * (L / 2);
+    hr::Word<L> v0[DEG + 1], v1[DEG];
+    {
+        uint32_t cb[DEG][4];
+        binom_limbs<DEG>(i0, cb);
+        row_start<L, DEG, 0>(T, cb, v0);
+        row_start<L, DEG, 1>(T, cb, v1);
+    }
+    row_full_to_stride<L, DEG + 1>(v0);
+    row_full_to_stride<L, DEG>(v1);
+    uint64_t* pa = a_out + sub * tau + i0;
+    uint64_t* pb = b_out + sub * tau + i0;
+    for (uint32_t s = 0; s < cnt; ++s) {
+        pb[(uint64_t)kStride * s] = top64(v0[0]);
+        pa[(uint64_t)kStride * s] = neg_top64(v1[0]);
+        row_step<L, DEG + 1>(v0);
+        row_step<L, DEG>(v1);
+    }
+}
+
 // Statistics are summed per wave, then added into one of kStatSlots
 // 64-byte slots picked by workgroup index, so that thousands of waves do
 // not queue on the same few addresses (atomics on one line are serialised:
@@ -1044,6 +1076,21 @@ __global__ __launch_bounds__(64) void k_stats_flush(unsigned long long* __restri
     }
 }
 
+// Partial quotients of each instance's closest-point walk (the work of the
+// search's filter step), for measurement.
+__global__ __launch_bounds__(kBlock) void k_search_steps(
+    const uint64_t* __restrict__ a, const uint64_t* __restrict__ b,
+    const uint32_t* __restrict__ N, uint64_t n, const uint64_t* __restrict__ lo,
+    const uint64_t* __restrict__ d, uint32_t group, uint32_t* __restrict__ steps) {
+    const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t g = i / group;
+    hr::HitIter it;
+    uint32_t st = 0;
+    hr::iter_init(it, a[i], b[i] - (lo ? lo[g] : 0), N[i], d[g], &st);
+    steps[i] = st;
+}
+
 __global__ __launch_bounds__(kBlock) void k_quot_check(const uint64_t* __restrict__ num,
                                                       const uint64_t* __restrict__ den,
                                                       uint64_t cap, uint64_t* __restrict__ out,
@@ -1176,8 +1223,17 @@ bool valid_poly(uint32_t degree, uint32_t width_bits) {
            (width_bits == 128 || width_bits == 192 || width_bits == 256);
 }
 
-// Packets per lane for tabulation: long enough to amortise the packet start
-// (straightforward shift), short enough to leave >= 4 lanes per CU slot.
+// Pieces per lane of hr_tabulate: long enough to amortise the packet start
+// (straightforward shift and step conversion), short enough that the grid
+// (one wave per 64 nu pieces of a sub-interval) has >= 16 waves per CU.
+uint32_t pick_nu_tab(uint64_t n_sub, uint32_t tau) {
+    uint32_t nu = kMaxNu;
+    while (nu > 1 && n_sub * ((tau + 64ull * nu - 1) / (64ull * nu)) < 256ull * 16) nu >>= 1;
+    return nu;
+}
+
+// Packets per lane for the fused pass: long enough to amortise the packet
+// start (straightforward shift), short enough to leave >= 4 lanes per CU slot.
 uint32_t pick_nu(uint64_t n_sub, uint32_t tau) {
     uint32_t nu = 16;
     while (nu > 1 && (uint64_t)n_sub * ((tau + nu - 1) / nu) < 256ull * 256 * 4) nu >>= 1;
@@ -1342,14 +1398,13 @@ hr_status hr_tabulate(hr_ctx* ctx, const uint64_t* table, uint32_t n_sub, uint32
     if (!table || !a_out || !b_out) return HR_EINVAL;
     if (hipSetDevice(ctx->device) != hipSuccess) return HR_EDEVICE;
     hipStream_t st = as_stream(stream);
-    const uint32_t nu = pick_nu(n_sub, tau);
-    if (nu > kMaxNu) return HR_EINVAL;
-    const uint64_t lanes = (uint64_t)n_sub * ((tau + nu - 1) / nu);
-    const uint64_t blocks = (lanes + 63) / 64;
+    const uint32_t nu = pick_nu_tab(n_sub, tau);
+    const uint64_t wps = (tau + 64ull * nu - 1) / (64ull * nu);   // waves per sub-interval
+    const uint64_t blocks = (uint64_t)n_sub * wps;
     if (blocks > 0xffffffffull) return HR_EINVAL;
     HR_DISPATCH(width_bits, degree,
                 (k_tabulate<L_, D_><<<dim3((uint32_t)blocks), dim3(64), 0, st>>>(
-                    table, n_sub, tau, nu, a_out, b_out)));
+                    table, tau, nu, (uint32_t)wps, a_out, b_out)));
     return launched();
 }
 
@@ -1414,14 +1469,20 @@ hr_status hr_subtables(hr_ctx* ctx, const uint64_t* upper, uint32_t upper_degree
     if (n_sub == 0) return HR_OK;
     if (!upper || !table_out) return HR_EINVAL;
     if (hipSetDevice(ctx->device) != hipSuccess) return HR_EDEVICE;
-    const uint64_t lanes = (uint64_t)n_sub * ((degree + 1) * (degree + 2) / 2);
-    const uint64_t blocks = (lanes + 63) / 64;
+    // lanes per sub-interval: the table's entries, and deg + 1 binomial
+    // lanes next to du + 1 shift lanes
+    const uint32_t need = std::max((degree + 1) * (degree + 2) / 2, degree + upper_degree + 2);
+    const uint32_t G = need <= 16 ? 16 : need <= 32 ? 32 : 64;
+    if (need > 64 || (64 / G) * ((degree + 1) * (upper_degree + 1) + upper_degree + 1) >
+                         (uint32_t)kSubtabWords)
+        return HR_EINVAL;
+    const uint64_t blocks = ((uint64_t)n_sub + 64 / G - 1) / (64 / G);
     if (blocks > 0xffffffffull) return HR_EINVAL;
     hipStream_t st = as_stream(stream);
 #define HR_SUBTAB(LU_)                                                                    \
     k_subtables<LU_><<<dim3((uint32_t)blocks), dim3(64), 0, st>>>(                        \
         upper, upper_degree, t_idx, t0, N_per, N, max_t, max_N, n_sub, degree, width_bits, \
-        table_out)
+        G, table_out)
     switch (upper_width / 32) {
         case 6: HR_SUBTAB(6); break;
         case 8: HR_SUBTAB(8); break;
@@ -1431,6 +1492,19 @@ hr_status hr_subtables(hr_ctx* ctx, const uint64_t* upper, uint32_t upper_degree
         default: return HR_EINVAL;
     }
 #undef HR_SUBTAB
+    return launched();
+}
+
+hr_status hr_search_steps(hr_ctx* ctx, const uint64_t* a, const uint64_t* b, const uint32_t* N,
+                          uint64_t n, const uint64_t* win_lo, const uint64_t* win_d,
+                          uint32_t group, uint32_t* steps, void* stream) {
+    if (!ctx || !win_d || group == 0 || n > 0xffffffffull) return HR_EINVAL;
+    if (n == 0) return HR_OK;
+    if (!a || !b || !N || !steps) return HR_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return HR_EDEVICE;
+    const uint64_t blocks = (n + kBlock - 1) / kBlock;
+    k_search_steps<<<dim3((uint32_t)blocks), dim3(kBlock), 0, as_stream(stream)>>>(
+        a, b, N, n, win_lo, win_d, group, steps);
     return launched();
 }
 

@@ -27,6 +27,7 @@ Transcendental values come from mpmath at W + guard + 64 bits.
 """
 from __future__ import annotations
 
+import math
 from dataclasses import dataclass
 from math import comb
 
@@ -445,7 +446,7 @@ def upper_table(fname: str, X0: float, count: int, s: int, mode: str, S: int, Du
                       upper_error(fname, X0, count, Du, uf))
 
 
-def upper_windows(U: UpperTable, N: int, tau: int, delta: int, W: int):
+def upper_windows_precise(U: UpperTable, N: int, tau: int, delta: int, W: int):
     """Degree-1 window (lo, d), thresholds and error bound mu of every
     sub-interval of the range whose table the device makes from U with
     pieces of N arguments, tau pieces, degree delta and width W.
@@ -519,3 +520,157 @@ def upper_windows(U: UpperTable, N: int, tau: int, delta: int, W: int):
                         min(int(mpmath.ceil(width * s64)) + 2, M64 - 1)], np.uint64)
         thr = np.array(value_bands(mu, eps), np.uint64)
     return win, thr, mu
+
+
+_UP = 1.0 + 2.0 ** -40          # covers the rounding of the float sums below
+
+
+def upper_windows(U: UpperTable, N: int, tau: int, delta: int, W: int):
+    """The bounds of upper_windows_precise in binary64 arithmetic (a few
+    hundred float operations instead of mpmath ones, for host preparation
+    in well under a millisecond).  Every quantity is a sum of products of
+    magnitudes (or, for the ranges of U^(j), a signed sum), evaluated with
+    relative error far below 2^-40 and then pushed outwards by 2^-40 of its
+    magnitude; the window and thresholds come from those outer bounds in
+    exact integer arithmetic, so they contain the precise ones."""
+    d = delta
+    if not 1 <= d <= min(U.Du, 8):
+        raise ValueError("degree must be between 1 and the upper degree")
+    Du = U.Du
+    c = [float(x) for x in U.coeffs]
+    ca = [abs(x) * _UP for x in c]
+    X = float(U.count + d * N + d)
+    fac = [float(math.factorial(k)) for k in range(Du + 1)]
+    Xp = [X ** e * _UP for e in range(Du + 1)]
+    Mx = [sum(ca[k] * fac[k] / fac[k - n] * Xp[k - n] for k in range(n, Du + 1)) * _UP
+          for n in range(Du + 1)]
+    en = [float(U.shift_error(n)) * _UP for n in range(Du + 1)]
+    cN = [float(comb(N - 1, j)) * _UP for j in range(Du + 1)]
+    cT = [float(comb(tau - 1, l)) * _UP for l in range(Du + 1)]
+    drop, keptE = {}, {}
+    for j in range(Du + 1):
+        for l in range(Du - j + 1):
+            if j + l > d:
+                drop[(j, l)] = float(N) ** l * Mx[j + l] * _UP
+            else:
+                keptE[(j, l)] = sum(en[n] * 2.0 ** l * float(comb(l * N, n - j)) * _UP
+                                    for n in range(j + l, Du + 1)) * _UP
+    e_drop = sum(v * cT[l] * cN[j] for (j, l), v in drop.items()) * _UP
+    e_shift = sum(v * cT[l] * cN[j] for (j, l), v in keptE.items()) * _UP
+    e_rw = float(round_bound(N, tau, d, W)) * _UP
+    mu = (float(U.e_approx) * _UP + e_drop + e_shift + e_rw) * _UP
+    t_lo = t_hi = 0.0
+    for j in range(2, d + 1):
+        base = c[j] * fac[j]
+        lo_j = hi_j = base
+        mag = abs(base)
+        for k in range(j + 1, Du + 1):
+            term = c[k] * fac[k] / fac[k - j] * X ** (k - j)
+            lo_j += min(term, 0.0)
+            hi_j += max(term, 0.0)
+            mag += abs(term)
+        slack = (sum(drop[(j, l)] * cT[l] for l in range(d - j + 1, Du - j + 1))
+                 + sum(keptE[(j, l)] * cT[l] for l in range(d - j + 1))
+                 + 2.0 ** (-W - 1) * sum(cT[l] for l in range(d - j + 1))) * _UP
+        margin = mag * 2.0 ** -40 + slack
+        t_lo += min(lo_j - margin, 0.0) * cN[j] * _UP
+        t_hi += max(hi_j + margin, 0.0) * cN[j] * _UP
+    t_lo *= _UP
+    t_hi *= _UP
+    mu64 = math.ceil(mu * 2.0 ** 64)
+    hi64 = math.ceil(t_hi * 2.0 ** 64)
+    lo64 = math.floor(t_lo * 2.0 ** 64)
+    e2 = 1 << (65 - U.s)                      # 2 eps 2^64
+    win = np.array([(-(mu64 + hi64 + 1)) % M64,
+                    min(e2 + 2 * mu64 + (hi64 - lo64) + (N + 1) + 4, M64 - 1)], np.uint64)
+    bands = []
+    for lo, hi in ((mu64, e2 - mu64 - 1), (e2 + mu64, M64 - mu64 - 1)):
+        if hi < lo or lo > M64 - 1 or hi < 0:
+            lo, hi = M64 - 1, 0
+        bands += [max(lo, 0), min(hi, M64 - 1)]
+    return win, np.array(bands, np.uint64), mu
+
+
+def _comb_f(x: np.ndarray, k: int) -> np.ndarray:
+    """C(x, k) of a float array of integers x >= 0 (0 where x < k), by the
+    product formula; relative error below (2 k + 1) 2^-53."""
+    out = np.ones_like(x, dtype=np.float64)
+    for i in range(k):
+        out = out * np.maximum(x - i, 0.0) / (i + 1)
+    return out
+
+
+def upper_windows_many(U: UpperTable, Ns, taus, delta: int, W: int):
+    """upper_windows for many (N, tau) pairs at once (numpy, binary64 with
+    the same outward margins): windows uint64 (n, 2), thresholds uint64
+    (n, 4).  The largest N sets the common offset range X of U's derivative
+    bounds, which only widens the others' bounds."""
+    d = delta
+    if not 1 <= d <= min(U.Du, 8):
+        raise ValueError("degree must be between 1 and the upper degree")
+    Ns = np.asarray(Ns, dtype=np.int64)
+    taus = np.asarray(taus, dtype=np.int64)
+    Nf, Tf = Ns.astype(np.float64), taus.astype(np.float64)
+    Du = U.Du
+    c = [float(x) for x in U.coeffs]
+    ca = [abs(x) * _UP for x in c]
+    X = float(U.count + d * int(Ns.max()) + d)
+    fac = [float(math.factorial(k)) for k in range(Du + 1)]
+    Xp = [X ** e * _UP for e in range(Du + 1)]
+    Mx = [sum(ca[k] * fac[k] / fac[k - n] * Xp[k - n] for k in range(n, Du + 1)) * _UP
+          for n in range(Du + 1)]
+    en = [float(U.shift_error(n)) * _UP for n in range(Du + 1)]
+    cN = [_comb_f(Nf - 1, j) * _UP for j in range(Du + 1)]
+    cT = [_comb_f(Tf - 1, l) * _UP for l in range(Du + 1)]
+    drop, keptE = {}, {}
+    for j in range(Du + 1):
+        for l in range(Du - j + 1):
+            if j + l > d:
+                drop[(j, l)] = Nf ** l * Mx[j + l] * _UP
+            else:
+                acc = np.zeros_like(Nf)
+                for n in range(j + l, Du + 1):
+                    acc = acc + en[n] * 2.0 ** l * _comb_f(l * Nf, n - j) * _UP
+                keptE[(j, l)] = acc * _UP
+    e_drop = sum(v * cT[l] * cN[j] for (j, l), v in drop.items()) * _UP
+    e_shift = sum(v * cT[l] * cN[j] for (j, l), v in keptE.items()) * _UP
+    rsum = sum(cN[j] * cT[l] for j in range(d + 1) for l in range(d - j + 1)) * _UP
+    e_rw = rsum * 2.0 ** -W * _UP
+    mu = (float(U.e_approx) * _UP + e_drop + e_shift + e_rw) * _UP
+    t_lo = np.zeros_like(Nf)
+    t_hi = np.zeros_like(Nf)
+    for j in range(2, d + 1):
+        base = c[j] * fac[j]
+        lo_j = hi_j = base
+        mag = abs(base)
+        for k in range(j + 1, Du + 1):
+            term = c[k] * fac[k] / fac[k - j] * X ** (k - j)
+            lo_j += min(term, 0.0)
+            hi_j += max(term, 0.0)
+            mag += abs(term)
+        slack = (sum((drop[(j, l)] * cT[l] for l in range(d - j + 1, Du - j + 1)),
+                     np.zeros_like(Nf))
+                 + sum(keptE[(j, l)] * cT[l] for l in range(d - j + 1))
+                 + 2.0 ** (-W - 1) * sum(cT[l] for l in range(d - j + 1))) * _UP
+        margin = mag * 2.0 ** -40 + slack
+        t_lo = t_lo + np.minimum(lo_j - margin, 0.0) * cN[j] * _UP
+        t_hi = t_hi + np.maximum(hi_j + margin, 0.0) * cN[j] * _UP
+    t_lo = t_lo * _UP
+    t_hi = t_hi * _UP
+    n = len(Ns)
+    win = np.zeros((n, 2), np.uint64)
+    thr = np.zeros((n, 4), np.uint64)
+    e2 = 1 << (65 - U.s)
+    for i in range(n):
+        mu64 = math.ceil(float(mu[i]) * 2.0 ** 64)
+        hi64 = math.ceil(float(t_hi[i]) * 2.0 ** 64)
+        lo64 = math.floor(float(t_lo[i]) * 2.0 ** 64)
+        win[i, 0] = (-(mu64 + hi64 + 1)) % M64
+        win[i, 1] = min(e2 + 2 * mu64 + (hi64 - lo64) + int(Ns[i]) + 1 + 4, M64 - 1)
+        bands = []
+        for lo, hi in ((mu64, e2 - mu64 - 1), (e2 + mu64, M64 - mu64 - 1)):
+            if hi < lo or lo > M64 - 1 or hi < 0:
+                lo, hi = M64 - 1, 0
+            bands += [max(lo, 0), min(hi, M64 - 1)]
+        thr[i] = bands
+    return win, thr

@@ -172,3 +172,10 @@ def test_each_parameter_check_returns_before_the_device():
         assert sst(**kw) == E, kw
     assert sst(n=_lib.HR_STATIC_MAX_INSTANCES + 1) == _lib.HR_ESCRATCH
     assert sst(n=_lib.HR_STATIC_MAX_INSTANCES) == DEV
+
+    def sps(n=1, group=1, win_d=p, steps=p):
+        return L.hr_search_steps(c, p, p, p, n, p, win_d, group, steps, None)
+    assert sps() == DEV
+    for kw in ({"group": 0}, {"n": 1 << 32}, {"win_d": None}, {"steps": None}):
+        assert sps(**kw) == E, kw
+    assert sps(n=0) == OK

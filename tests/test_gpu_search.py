@@ -180,3 +180,35 @@ def test_device_quotient_routine_exact():
         want_r = np.array([n % d if n // d < cap else M - 1 for n, d in zip(nums, dens)], np.uint64)
         bad = np.nonzero((got != want) | (got_r != want_r))[0]
         assert bad.size == 0, [(nums[i], dens[i], cap, int(got[i]), int(want[i])) for i in bad[:5]]
+
+
+def test_search_steps_match_pipeline_statistics():
+    """hr_search_steps on the tabulated pieces of a small exp range counts
+    the same partial quotients as the fused pass's statistics (both run
+    the closest-point walk on identical (a, b, N, window))."""
+    import numpy as np
+    import torch
+
+    from paper_1211_3056_amd import _lib, api, pipeline
+    from paper_1211_3056_amd.prep import JobSpec, prepare
+    spec = JobSpec("exp", 1.0, 1 << 22, 12, "rn", 1 << 10, 1 << 6, 3, 192)
+    P = prepare(spec)
+    table, win, thr = pipeline.upload(P)
+    ctx = api.context()
+    _, st = api.pipeline(table, spec.n_sub, spec.delta, spec.tau, spec.W, spec.N, win, thr)
+    stats = torch.zeros(8, dtype=torch.uint64, device="cuda")
+    out = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    count = torch.zeros(1, dtype=torch.uint64, device="cuda")
+    _lib.hr_pipeline(ctx, table, spec.n_sub, spec.delta, spec.tau, spec.W, spec.N, win, thr,
+                     out, (1 << 20) // _lib.RESULT_BYTES, count, stats)
+    a, b = api.tabulate(table, spec.n_sub, spec.delta, spec.tau, spec.W)
+    n = spec.n_sub * spec.tau
+    N = api.to_dev(np.full(n, spec.N, np.uint32), torch.uint32)
+    lo = api.to_dev(P.win[:, 0], torch.uint64)
+    d = api.to_dev(P.win[:, 1], torch.uint64)
+    steps = torch.empty(n, dtype=torch.uint32, device="cuda")
+    _lib.hr_search_steps(ctx, a, b, N, lo, d, spec.tau, steps)
+    torch.cuda.synchronize()
+    s = steps.cpu().numpy().astype(np.int64)
+    assert s.min() >= 1 and s.max() <= 64
+    assert int(s.sum()) == int(stats.cpu().numpy()[3])

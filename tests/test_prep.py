@@ -239,3 +239,48 @@ def test_upper_error_budget_shapes():
     assert int(P.win[:, 1].max()) <= int(win[1]) < int(P.win[:, 1].max()) * 1.001
     U6 = upper_table("exp", 1.0, 1 << 40, 32, "rn", 1 << 28, 6, 320)
     assert U6.e_approx > mpmath.mpf(2) ** (-32 - 12)
+
+
+@pytest.mark.parametrize("fname,X0,count,S,Du,Wu,N,tau,d,W,s", [
+    ("exp", 1.0, 1 << 40, 1 << 28, 7, 320, 1 << 18, 1 << 10, 4, 256, 32),
+    ("exp", 1.0, 1 << 32, 1 << 24, 4, 256, 1 << 16, 1 << 8, 3, 192, 24),
+    ("log", 3.0, 1 << 36, 1 << 28, 6, 320, 5000, 53688, 3, 128, 28),
+    ("sin", 1.0, 1 << 34, 1 << 26, 6, 256, 1 << 14, 1 << 12, 3, 128, 20),
+    ("exp2", 1.25, 1 << 30, 1 << 20, 5, 192, 1 << 10, 1 << 10, 2, 128, 28)])
+def test_float_windows_contain_precise_ones(fname, X0, count, S, Du, Wu, N, tau, d, W, s):
+    """The binary64 bounds of upper_windows contain the 192-bit ones: the
+    window starts at or before the precise start and ends at or after its
+    end, and each certainty band lies inside the precise band."""
+    from paper_1211_3056_amd.prep import upper_table, upper_windows, upper_windows_precise
+    U = upper_table(fname, X0, count, s, "rn", S, Du, Wu)
+    wf, tf, muf = upper_windows(U, N, tau, d, W)
+    wp, tp, mup = upper_windows_precise(U, N, tau, d, W)
+    shift = (int(wp[0]) - int(wf[0])) % (1 << 64)
+    assert shift < 1 << 16
+    assert int(wf[1]) >= int(wp[1]) + shift
+    assert muf >= float(mup)
+    for b in (0, 2):
+        lo_f, hi_f, lo_p, hi_p = int(tf[b]), int(tf[b + 1]), int(tp[b]), int(tp[b + 1])
+        if lo_f <= hi_f:
+            assert lo_p <= lo_f and hi_f <= hi_p
+
+
+def test_vectorised_windows_contain_precise_ones():
+    """upper_windows_many over uneven piece lengths (the batched workload's
+    shapes) contains the 192-bit bounds of every (N, tau) pair."""
+    from paper_1211_3056_amd.prep import upper_table, upper_windows_many, upper_windows_precise
+    U = upper_table("exp", 1.0, 1 << 34, 28, "rn", 1 << 28, 6, 320)
+    rng = synth.rng(9)
+    Ns = rng.integers(1 << 12, (1 << 20) + 1, 12)
+    Ns[0], Ns[1] = 1 << 12, 1 << 20
+    taus = -(-(1 << 28) // Ns)
+    taus[2] = 1
+    win, thr = upper_windows_many(U, Ns, taus, 3, 128)
+    for i in range(len(Ns)):
+        wp, tp, _ = upper_windows_precise(U, int(Ns[i]), int(taus[i]), 3, 128)
+        # the common offset range (largest N) may start the window earlier
+        shift = (int(wp[0]) - int(win[i, 0])) % (1 << 64)
+        assert shift < int(wp[1]) // 64 and int(win[i, 1]) >= int(wp[1]) + shift, i
+        for b in (0, 2):
+            if int(thr[i, b]) <= int(thr[i, b + 1]):
+                assert int(tp[b]) <= int(thr[i, b]) and int(thr[i, b + 1]) <= int(tp[b + 1])
