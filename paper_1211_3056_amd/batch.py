@@ -5,9 +5,11 @@ A job covers `count` consecutive binary64 arguments from X0.  It is cut
 into sub-intervals of `sub_len` arguments (the last one shorter if needed),
 each with its own piece length N (given per sub-interval, given once, or
 chosen by the autotuner) and a partial last piece when N does not divide
-the sub-interval.  Every sub-interval gets its table, window and thresholds
-from ``prep.SubPreparer``; its pieces are split into work items
-(``autotune.split_sub``).
+the sub-interval.  The host makes one upper table per range of the job
+(``plan.upper_ranges``) and the windows and thresholds of its
+sub-intervals; the device makes every sub-interval's table from the upper
+tables (hr_subtables) into one table pool; the pieces are split into work
+items (``autotune.split_sub``).
 
 Two forms run the same kernel on the same items:
   plain    one launch per job (one wave per item), results read back per job;
@@ -24,8 +26,9 @@ import numpy as np
 import torch
 
 from . import _lib, api, autotune
-from .plan import BatchJob, PlannedJob, PlannedSub, plan_job, split_by_job  # noqa: F401
-from .prep import JobSpec, SubPreparer, is_hr
+from .plan import (BatchJob, PlannedJob, PlannedSub, TablePlan, job_items,  # noqa: F401
+                   job_windows, plan_job, split_by_job, sub_costs, upper_ranges)
+from .prep import JobSpec, is_hr
 
 M64 = 1 << 64
 
@@ -33,7 +36,8 @@ M64 = 1 << 64
 @dataclass
 class Plan:
     jobs: list                # PlannedJob, in job order
-    pool: np.ndarray          # uint64 table pool
+    tables: list              # (TablePlan, word offset of its table region in the pool)
+    pool_words: int           # size of the device table pool
     items: np.ndarray         # api.ITEM_DTYPE, grouped by job then sub (plain order)
     variants: list            # (W, delta) of each item
     prep_s: float = 0.0
@@ -43,42 +47,64 @@ class Plan:
 
 
 def build_plan(jobs, target_items: int = 16384, model=autotune.MODEL) -> Plan:
-    """Plan, prepare and split every job into work items."""
+    """Plan every job (upper tables, windows) and split it into work items of
+    about equal modelled cost over the whole batch."""
     t0 = time.time()
-    planned = [plan_job(j) for j in jobs]
-    tables, item_rows, variants = [], [], []
-    offset = 0
-    total_cost = 0.0
     staged = []
-    for pj in planned:
-        prep = SubPreparer(pj.job.fname, pj.job.X0, pj.job.s, pj.job.mode, pj.delta, pj.W, pj.uf)
-        for t, sp in enumerate(pj.subs):
-            table, win, thr = prep.prepare(sp.start, sp.length, sp.N)
-            cand = sp.length * float(win[1]) / 2.0 ** 64
-            cost = model.cost(sp.pieces, sp.N, cand)
-            total_cost += cost
-            staged.append((pj, t, sp, table, win, thr, cand, cost))
-    target = max(total_cost / target_items, 1e-9)
-    for pj, t, sp, table, win, thr, cand, cost in staged:
-        tables.append(table.reshape(-1))
-        last_piece = sp.pieces - 1 if sp.length % sp.N else 0xFFFFFFFF
-        last_N = sp.length - (sp.pieces - 1) * sp.N
-        for piece0, npieces, nu in autotune.split_sub(sp.pieces, sp.N, cand, target, model):
-            item_rows.append((offset, int(win[0]), int(win[1]), tuple(int(x) for x in thr),
-                              pj.job.job_id, t, piece0, npieces, nu, sp.N, last_piece, last_N))
-            variants.append((pj.W, pj.delta))
-        offset += table.size
-    items = np.array(item_rows, dtype=api.ITEM_DTYPE)
-    pool = np.concatenate(tables) if tables else np.zeros(1, np.uint64)
-    return Plan(planned, pool, items, variants, time.time() - t0)
+    total = 0.0
+    for j in jobs:
+        pj = plan_job(j)
+        ranges = upper_ranges(pj)
+        win, thr = job_windows(pj, ranges)
+        total += sub_costs(pj, win, model)
+        staged.append((pj, ranges, win, thr))
+    target = max(total / target_items, 1e-9)
+    tables, item_parts, variants = [], [], []
+    base = 0
+    for pj, ranges, win, thr in staged:
+        items = job_items(pj, win, thr, target, model)
+        tp = TablePlan(pj.job, pj.delta, pj.W, str(pj.uf),
+                       [(sp.start, sp.length, sp.N) for sp in pj.subs],
+                       [(lo, hi, U.Du, U.Wu, U.words) for lo, hi, U in ranges],
+                       np.array([sp.N for sp in pj.subs], np.uint32), win, thr, items)
+        tables.append((tp, base))
+        items = items.copy()
+        items["table"] += base
+        item_parts.append(items)
+        variants += [(pj.W, pj.delta)] * len(items)
+        base += tp.table_words
+    items = np.concatenate(item_parts) if item_parts else np.zeros(0, api.ITEM_DTYPE)
+    return Plan([s[0] for s in staged], tables, max(base, 1), items, variants, time.time() - t0)
+
+
+def make_tables(ctx, pool, base: int, tp: TablePlan, stream=None):
+    """Launch hr_subtables for every range of one job: its sub-interval tables
+    into pool[base:] (words), on the device."""
+    E = tp.entries
+    L = tp.W // 64
+    for lo, hi, Du, Wu, words in tp.ranges:
+        upper = api.to_dev(words.reshape(-1), torch.uint64, pool.device)
+        Ns = api.to_dev(tp.Ns[lo:hi], torch.uint32, pool.device)
+        out = pool[base + lo * E * L: base + hi * E * L]
+        _lib.hr_subtables(ctx, upper, Du, Wu, None, 0, Ns, 0, hi - lo - 1, int(tp.Ns[lo:hi].max()),
+                          hi - lo, tp.delta, tp.W, out, stream)
 
 
 class DevicePlan:
-    """A plan resident in HBM: pool and items (plain and cost-sorted orders)."""
+    """A plan resident in HBM: the table pool (made on the device from the
+    upper tables) and the items (plain and cost-sorted orders)."""
 
-    def __init__(self, plan: Plan, model=autotune.MODEL, device="cuda"):
+    def __init__(self, plan: Plan, model=autotune.MODEL, device="cuda", ctx=None):
         self.plan = plan
-        self.pool = api.to_dev(plan.pool, torch.uint64, device)
+        ctx = ctx or api.context()
+        self.pool = torch.empty(plan.pool_words, dtype=torch.uint64, device=device)
+        ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        ev[0].record()
+        for tp, base in plan.tables:
+            make_tables(ctx, self.pool, base, tp)
+        ev[1].record()
+        torch.cuda.synchronize()
+        self.tables_ms = ev[0].elapsed_time(ev[1])
         raw = plan.items.view(np.uint8).reshape(-1)
         self.items = api.to_dev(raw, torch.uint8, device)
         # batched order: by variant, then decreasing modelled cost

@@ -2,19 +2,23 @@
 
 Jobs (function, argument range, threshold) arrive at given times.  Each job
 goes through
-  queued   -> preparing (host tables in a worker process)
+  queued   -> preparing (upper tables, windows and work items, in a worker
+              process)
            -> ready     (waiting for device memory and a slot)
-           -> admitted  (tables and items resident in HBM)
+           -> admitted  (its sub-interval tables made on the device, from
+                         its upper tables, in its region of the table arena)
            -> done      (results read back, undecided values decided)
 or failed (its preparation or launch raised; other jobs are unaffected).
 
-Admission is by HBM footprint (tables + work items + a result reserve)
-against a budget (default: the device's free memory) and by a cap on jobs
-resident at once.  Every device step launches the fused persistent kernel
-over the work items of all admitted jobs that have not run yet, so jobs that
-arrived while others were on the GPU join the next launch (iteration-level
-continuous batching); host preparation of arriving jobs overlaps device
-work.  A job's results do not depend on which other jobs share its launch.
+Admission is by HBM footprint (tables, upper tables and work items) against
+a budget (default: the arena's size, at most 90% of the device's free
+memory) and by a cap on jobs resident at once.  Admitted tables live in one
+device arena at offsets from a free list, so a step needs no copy of them.
+Every device step launches the fused persistent kernel over the work items
+of all admitted jobs that have not run yet, so jobs that arrived while
+others were on the GPU join the next launch (iteration-level continuous
+batching); host preparation of arriving jobs overlaps device work.  A job's
+results do not depend on which other jobs share its launch.
 
 Preparation workers are processes started from a forkserver created before
 the GPU is touched, so no process that has initialised the GPU forks or
@@ -29,83 +33,18 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import autotune
-from .plan import ITEM_DTYPE, RESULT_DTYPE, BatchJob, plan_job, split_by_job
-from .prep import JobSpec, SubPreparer, is_hr
+from .plan import ITEM_DTYPE, RESULT_DTYPE, BatchJob, TablePlan, plan_tables, split_by_job  # noqa: F401
+from .prep import JobSpec, is_hr
 
-RESULT_RESERVE = 64 * 32          # bytes reserved per job for its result records
-
-
-@dataclass
-class Prepared:
-    """Host-side output of preparing one job (picklable)."""
-    job: BatchJob
-    delta: int
-    W: int
-    uf: str
-    subs: list                    # (start, length, N)
-    tables: np.ndarray            # uint64, concatenated sub-interval tables
-    items: np.ndarray             # ITEM_DTYPE, table offsets relative to `tables`
-    prep_s: float
-
-    @property
-    def footprint(self) -> int:
-        return int(self.tables.nbytes + self.items.nbytes + RESULT_RESERVE)
+Prepared = TablePlan
 
 
-def prepare_job(job: BatchJob, target_item_ns: float = 2000.0, part=None) -> Prepared:
-    """Plan and prepare one job (runs in a worker process); part = (lo, hi)
-    restricts it to sub-intervals lo..hi-1 (see merge_parts)."""
-    t0 = time.time()
-    pj = plan_job(job)
-    sp = SubPreparer(job.fname, job.X0, job.s, job.mode, pj.delta, pj.W, pj.uf)
-    tables, rows = [], []
-    off = 0
-    lo, hi = part if part is not None else (0, len(pj.subs))
-    for t in range(lo, hi):
-        s = pj.subs[t]
-        table, win, thr = sp.prepare(s.start, s.length, s.N)
-        cand = s.length * float(win[1]) / 2.0 ** 64
-        last_piece = s.pieces - 1 if s.length % s.N else 0xFFFFFFFF
-        last_N = s.length - (s.pieces - 1) * s.N
-        for piece0, npieces, nu in autotune.split_sub(s.pieces, s.N, cand, target_item_ns):
-            rows.append((off, int(win[0]), int(win[1]), tuple(int(x) for x in thr), job.job_id,
-                         t, piece0, npieces, nu, s.N, last_piece, last_N))
-        tables.append(table.reshape(-1))
-        off += table.size
-    return Prepared(job, pj.delta, pj.W, str(pj.uf),
-                    [(s.start, s.length, s.N) for s in pj.subs[lo:hi]],
-                    np.concatenate(tables), np.array(rows, dtype=ITEM_DTYPE), time.time() - t0)
+def prepare_job(job: BatchJob, target_item_ns: float = 2000.0) -> TablePlan:
+    """Plan and prepare one job (runs in a worker process)."""
+    return plan_tables(job, target_item_ns)
 
 
-def merge_parts(parts) -> Prepared:
-    """One Prepared from the parts of a job prepared over consecutive
-    sub-interval ranges, in order: tables concatenated, item table offsets
-    moved accordingly (item sub indices are already global)."""
-    if len(parts) == 1:
-        return parts[0]
-    items, base = [], 0
-    for p in parts:
-        it = p.items.copy()
-        it["table"] += base
-        base += p.tables.size
-        items.append(it)
-    p0 = parts[0]
-    return Prepared(p0.job, p0.delta, p0.W, p0.uf, [s for p in parts for s in p.subs],
-                    np.concatenate([p.tables for p in parts]), np.concatenate(items),
-                    max(p.prep_s for p in parts))
-
-
-def job_parts(job: BatchJob, subs_per_part: int):
-    """Sub-interval ranges (lo, hi) of a job, for preparation by several
-    workers; one range for jobs of at most subs_per_part sub-intervals."""
-    n = -(-job.count // job.sub_len)
-    if n <= subs_per_part:
-        return [None]
-    return [(lo, min(lo + subs_per_part, n)) for lo in range(0, n, subs_per_part)]
-
-
-def decide_results(prep: Prepared, res: np.ndarray) -> np.ndarray:
+def decide_results(prep: TablePlan, res: np.ndarray) -> np.ndarray:
     """Sorted HR offsets (int64 array) of one job from its result records."""
     from mpmath import mpf
     if len(res) == 0:
@@ -123,12 +62,45 @@ def decide_results(prep: Prepared, res: np.ndarray) -> np.ndarray:
     return np.sort(sure)
 
 
+class Arena:
+    """First-fit allocator of word ranges [offset, offset + n) in one device
+    buffer of `words` words; freed ranges merge with free neighbours."""
+
+    def __init__(self, words: int):
+        self.words = words
+        self.free = [(0, words)]          # sorted, disjoint (offset, length)
+
+    def alloc(self, n: int):
+        for i, (off, ln) in enumerate(self.free):
+            if ln >= n:
+                if ln == n:
+                    self.free.pop(i)
+                else:
+                    self.free[i] = (off + n, ln - n)
+                return off
+        return None
+
+    def release(self, off: int, n: int):
+        import bisect
+        i = bisect.bisect_left(self.free, (off, 0))
+        self.free.insert(i, (off, n))
+        if i + 1 < len(self.free) and off + n == self.free[i + 1][0]:
+            self.free[i] = (off, n + self.free.pop(i + 1)[1])
+        if i > 0 and self.free[i - 1][0] + self.free[i - 1][1] == off:
+            po, pn = self.free.pop(i - 1)
+            self.free[i - 1] = (po, pn + self.free[i - 1][1])
+
+    @property
+    def free_words(self) -> int:
+        return sum(n for _, n in self.free)
+
+
 @dataclass
 class JobState:
     job: BatchJob
     arrival: float
     status: str = "queued"
-    prep: Prepared | None = None
+    prep: TablePlan | None = None
     t_ready: float = 0.0
     t_admit: float = 0.0
     t_done: float = 0.0
@@ -136,8 +108,6 @@ class JobState:
     records: np.ndarray | None = None   # result records, device order (plan.canonical sorts)
     error: str = ""
     dev: object = None            # device handle of the admitted job (backend-specific)
-    parts: list = field(default_factory=list)   # prepared parts while preparing
-    left: int = 0                 # parts still being prepared
 
     @property
     def latency(self) -> float:
@@ -145,10 +115,10 @@ class JobState:
 
 
 class GpuBackend:
-    """Device side: uploads admitted jobs, launches the persistent kernel over
-    their items, returns result records per job."""
+    """Device side: makes admitted jobs' tables in the arena, launches the
+    persistent kernel over their items, returns result records per job."""
 
-    def __init__(self, cap: int = 1 << 20, waves: int | None = None):
+    def __init__(self, cap: int = 1 << 20, waves: int | None = None, arena_bytes: int = 1 << 30):
         import torch
 
         from . import _lib, api
@@ -157,6 +127,9 @@ class GpuBackend:
         self.ctx = api.context()
         self.cap = cap
         self.waves = waves or device_waves()
+        self.arena_t = torch.empty(arena_bytes // 8, dtype=torch.uint64, device="cuda")
+        self.arena = Arena(arena_bytes // 8)
+        self.capacity_bytes = arena_bytes
         self.out = torch.empty(cap * _lib.RESULT_BYTES, dtype=torch.uint8, device="cuda")
         self.count = torch.zeros(1, dtype=torch.uint64, device="cuda")
         self.stats = torch.zeros(8, dtype=torch.uint64, device="cuda")
@@ -165,23 +138,34 @@ class GpuBackend:
     def free_memory(self) -> int:
         return int(self.torch.cuda.mem_get_info()[0])
 
-    def admit(self, st: JobState):
-        st.dev = self.api.to_dev(st.prep.tables, self.torch.uint64)
+    def admit(self, st: JobState) -> bool:
+        """Make the job's tables in a region of the arena; False (nothing
+        done) if no free range is long enough."""
+        from .batch import make_tables
+        off = self.arena.alloc(st.prep.table_words)
+        if off is None:
+            return False
+        try:
+            make_tables(self.ctx, self.arena_t, off, st.prep)
+        except Exception:
+            self.arena.release(off, st.prep.table_words)
+            raise
+        st.dev = off
+        return True
 
     def release(self, st: JobState):
-        st.dev = None
+        if st.dev is not None:
+            self.arena.release(st.dev, st.prep.table_words)
+            st.dev = None
 
     def step(self, states):
         """One launch over every item of the given admitted jobs; returns the
         result records of each job (list aligned with states)."""
         torch, _lib, api = self.torch, self._lib, self.api
-        pool = torch.cat([s.dev for s in states])
-        items, base = [], 0
         groups = {}
         for s in states:
             it = s.prep.items.copy()
-            it["table"] += base
-            base += s.prep.tables.size
+            it["table"] += s.dev
             groups.setdefault((s.prep.W, s.prep.delta), []).append(it)
         launches = []
         for (W, d), parts in sorted(groups.items()):
@@ -190,8 +174,8 @@ class GpuBackend:
         while True:
             self.count.zero_()
             for W, d, n_items, dev_items in launches:
-                _lib.hr_batch_run(self.ctx, pool, dev_items, n_items, W, d, self.waves, self.out,
-                                  self.cap, self.count, self.stats)
+                _lib.hr_batch_run(self.ctx, self.arena_t, dev_items, n_items, W, d, self.waves,
+                                  self.out, self.cap, self.count, self.stats)
             torch.cuda.synchronize()
             n = api._u64_scalar(self.count)
             if n <= self.cap:
@@ -214,6 +198,8 @@ def make_pool(workers: int):
 
 def _warm(_):
     import mpmath  # noqa: F401
+
+    from . import plan  # noqa: F401
     return 0
 
 
@@ -221,11 +207,14 @@ class Server:
     """Continuous-batching server over a device backend."""
 
     def __init__(self, backend, pool, hbm_budget: int | None = None, max_resident: int = 4096,
-                 clock=time.perf_counter, subs_per_part: int = 16):
+                 clock=time.perf_counter):
         self.backend = backend
         self.pool = pool
-        self.subs_per_part = subs_per_part   # large jobs are prepared by several workers
-        self.budget = hbm_budget if hbm_budget is not None else int(0.9 * backend.free_memory())
+        cap = getattr(backend, "capacity_bytes", None)
+        budget = int(0.9 * backend.free_memory())
+        if cap is not None:
+            budget = min(budget, cap)
+        self.budget = hbm_budget if hbm_budget is not None else budget
         self.max_resident = max_resident
         self.clock = clock
         self.used = 0
@@ -259,32 +248,19 @@ class Server:
                     ready.append(st)
                     continue
                 st.status = "preparing"
-                # split a large job over several workers only while workers
-                # are idle: it cuts that job's latency, not the throughput
-                idle = len(futures) < getattr(self.pool, "_max_workers", 1)
-                parts = job_parts(st.job, self.subs_per_part) if idle else [None]
-                st.parts, st.left = [None] * len(parts), len(parts)
-                for i, part in enumerate(parts):
-                    futures[self.pool.submit(prepare_job, st.job, 2000.0, part)] = (st, i)
-            # finished preparations -> ready queue (arrival order kept by FIFO of completion)
+                futures[self.pool.submit(prepare_job, st.job, 2000.0)] = st
+            # finished preparations -> ready queue
             for fut in [f for f in futures if f.done()]:
-                st, i = futures.pop(fut)
-                if st.status == "failed":    # another part of it failed already
-                    continue
+                st = futures.pop(fut)
                 try:
-                    st.parts[i] = fut.result()
+                    st.prep = fut.result()
                 except Exception as e:       # a bad job fails alone
                     st.status, st.error, st.t_done = "failed", repr(e), now()
-                    st.parts = []
                     done += 1
                     continue
-                st.left -= 1
-                if st.left == 0:
-                    st.prep = merge_parts(st.parts)
-                    st.parts = []
-                    st.status = "ready"
-                    st.t_ready = now()
-                    ready.append(st)
+                st.status = "ready"
+                st.t_ready = now()
+                ready.append(st)
             ready.sort(key=lambda s: s.arrival)
             # admission by footprint and resident slots
             while ready:
@@ -298,13 +274,23 @@ class Server:
                 if self.used + fp > self.budget or len(resident) >= self.max_resident:
                     self.blocked_admissions += 1
                     break
-                ready.pop(0)
                 try:
-                    self.backend.admit(st)
+                    placed = self.backend.admit(st)
                 except Exception as e:
+                    ready.pop(0)
                     st.status, st.error, st.t_done = "failed", repr(e), now()
                     done += 1
                     continue
+                if placed is False:          # no free range long enough yet
+                    if self.used == 0:           # and nothing will free one
+                        ready.pop(0)
+                        st.status, st.t_done = "failed", now()
+                        st.error = "job larger than the table arena"
+                        done += 1
+                        continue
+                    self.blocked_admissions += 1
+                    break
+                ready.pop(0)
                 self.used += fp
                 self.peak_used = max(self.peak_used, self.used)
                 st.status, st.t_admit = "admitted", now()

@@ -137,26 +137,61 @@ def test_split_by_job_equals_filter():
             assert canonical(got).tobytes() == canonical(want).tobytes()
 
 
-def test_parts_merge_to_the_whole_job():
-    """A job prepared as ranges of sub-intervals and merged equals the job
-    prepared in one piece (tables, items with their table offsets, subs)."""
-    job = BatchJob("sin", 1.25, 5 * (1 << 16) + 123, 12, "rn", sub_len=1 << 16, N=[1000, 777, 4096, 333, 5000, 64], job_id=3)
-    whole = serve.prepare_job(job)
-    parts = serve.job_parts(job, 2)
-    assert parts == [(0, 2), (2, 4), (4, 6)]
-    merged = serve.merge_parts([serve.prepare_job(job, part=p) for p in parts])
-    assert np.array_equal(merged.tables, whole.tables)
-    assert merged.items.tobytes() == whole.items.tobytes()
-    assert merged.subs == whole.subs and (merged.delta, merged.W) == (whole.delta, whole.W)
-    assert serve.job_parts(job, 16) == [None]
+def test_arena_first_fit_and_merging():
+    a = serve.Arena(100)
+    x = a.alloc(30)
+    y = a.alloc(30)
+    z = a.alloc(30)
+    assert (x, y, z) == (0, 30, 60) and a.alloc(11) is None and a.alloc(10) == 90
+    a.release(y, 30)
+    assert a.alloc(31) is None
+    a.release(x, 30)                      # merges with y's range
+    assert a.free == [(0, 60)]
+    assert a.alloc(45) == 0
+    a.release(0, 45)
+    a.release(z, 30)
+    a.release(90, 10)
+    assert a.free == [(0, 100)] and a.free_words == 100
 
 
-def test_served_in_parts_equals_whole(pool):
-    be = FakeBackend()
-    jobs = [BatchJob("exp", 1.0 + 0.01 * i, 9 * (1 << 14), 20, "rn", sub_len=1 << 14, N=1 << 8, job_id=i) for i in range(3)]
-    a = serve.Server(be, pool, hbm_budget=1 << 30, subs_per_part=2).serve(jobs, np.zeros(3), realtime=False)
-    b = serve.Server(be, pool, hbm_budget=1 << 30, subs_per_part=64).serve(jobs, np.zeros(3), realtime=False)
-    for x, y in zip(a, b):
-        assert x.status == y.status == "done"
-        assert np.array_equal(x.prep.tables, y.prep.tables)
-        assert x.prep.items.tobytes() == y.prep.items.tobytes()
+def test_arena_against_occupancy_map():
+    """Random alloc/release sequences: ranges never overlap, every word is
+    either free or held, and freed space always merges back."""
+    rng = np.random.default_rng(7)
+    a = serve.Arena(1000)
+    held = {}
+    occ = np.zeros(1000, bool)
+    for _ in range(3000):
+        if held and rng.random() < 0.45:
+            off = list(held)[int(rng.integers(len(held)))]
+            n = held.pop(off)
+            assert occ[off:off + n].all()
+            occ[off:off + n] = False
+            a.release(off, n)
+        else:
+            n = int(rng.integers(1, 120))
+            off = a.alloc(n)
+            if off is None:
+                runs = np.diff(np.flatnonzero(np.diff(np.concatenate([[1], occ.astype(int), [1]]))))
+                assert n > max(runs[::2], default=0)   # no free run was long enough
+                continue
+            assert not occ[off:off + n].any()
+            occ[off:off + n] = True
+            held[off] = n
+        assert a.free_words == int((~occ).sum())
+        assert all(o1 + n1 < o2 for (o1, n1), (o2, _) in zip(a.free, a.free[1:]))
+    for off, n in held.items():
+        a.release(off, n)
+    assert a.free == [(0, 1000)]
+
+
+def test_prepared_job_is_deterministic_and_sized():
+    job = BatchJob("sin", 1.25, 5 * (1 << 16) + 123, 12, "rn", sub_len=1 << 16,
+                   N=[1000, 777, 4096, 333, 5000, 64], job_id=3)
+    a, b = serve.prepare_job(job), serve.prepare_job(job)
+    assert a.items.tobytes() == b.items.tobytes()
+    assert [r[4].tobytes() for r in a.ranges] == [r[4].tobytes() for r in b.ranges]
+    assert a.table_words == 6 * a.entries * (a.W // 64)
+    assert a.footprint >= a.table_words * 8 + a.items.nbytes
+    # item table offsets address the job's own table region, sub-interval by sub-interval
+    assert set(a.items["table"].tolist()) == {t * a.entries * (a.W // 64) for t in range(6)}
