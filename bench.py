@@ -257,6 +257,8 @@ def main():
     line["tabulation"] = bench_tabulation(spec, step.table, ctx, stream, args.steps)
     line["config1"] = bench_config1(ctx, stream, args.steps)
     line["config2"] = bench_config2(ctx, stream, args)
+    line["filters"] = bench_filters(ctx, stream)
+    line["cpu_simd"] = bench_cpu_simd(step, ctx, stream)
     if not args.no_plain:
         line["plain_form"] = bench_plain(step, ctx, stream)
     if not args.no_batch:
@@ -409,6 +411,130 @@ def bench_plain(step, ctx, stream, reps=3):
     return {"device_ms": dev_ms, "wall_ms": wall * 1000, "value": sp.count / (dev_ms / 1000),
             "candidates": n_cand, "hr_cases": n_hr,
             "launches": "hr_tabulate, hr_search (3 kernels), hr_recheck"}
+
+
+def wave_stats(it, width):
+    """min / max / mean of per-instance loop passes, and the mean over groups
+    of `width` consecutive lanes of the idle fraction 1 - sum / (width max)
+    (the paper's NMDM, Sec. 2.2)."""
+    import numpy as np
+    it = it.astype(np.float64)
+    g = it[: len(it) // width * width].reshape(-1, width)
+    mx = g.max(axis=1)
+    nmdm = np.where(mx > 0, 1.0 - g.mean(axis=1) / np.maximum(mx, 1), 0.0)
+    return {"min": int(it.min()), "max": int(it.max()), "mean": float(it.mean()),
+            "nmdm": float(nmdm.mean())}
+
+
+def bench_filters(ctx, stream, reps=5):
+    """The paper's lower-bound tests against the exact walk on the Table 3
+    workload's pieces: exp on [1, 1 + 2^-13) (2^39 arguments, directed,
+    eps = 2^-32, pieces of N = 2^15, degree 3 at 192 bits; 2^24 pieces,
+    tables made on the device).  Per test: kernel time (HIP events), loop
+    passes per piece (min / max / mean) and the idle fraction of a 64-lane
+    wave and of a 32-lane group (the paper's warp), and the share of pieces
+    it certifies.  The exact walk's partial quotients come from
+    hr_search_steps, its time from hr_search over the same pieces."""
+    import numpy as np
+    import torch
+
+    from paper_1211_3056_amd import _lib, api, autotune, pipeline
+    from paper_1211_3056_amd.prep import JobSpec
+    spec = JobSpec("exp", 1.0, 1 << 39, 32, "dir", 1 << 15, 1 << 13, 3, 192)
+    Du = autotune.choose_upper_degree(spec.fname, spec.X0, spec.count, spec.s, spec.delta)
+    P = pipeline.UpperPrepared(spec, Du, 320)
+    upper, win, thr = pipeline.upload_upper(P)
+    table = pipeline.make_tables(P, upper, ctx=ctx, stream=stream)
+    a, b = api.tabulate(table, spec.n_sub, spec.delta, spec.tau, spec.W, ctx=ctx, stream=stream)
+    n = a.numel()
+    N = api.to_dev(np.full(n, spec.N, np.uint32), torch.uint32)
+    lo = api.to_dev(np.full(1, P.win[0], np.uint64), torch.uint64)
+    d = api.to_dev(np.full(1, P.win[1], np.uint64), torch.uint64)
+    passed = torch.empty(n, dtype=torch.uint8, device="cuda")
+    iters = torch.empty(n, dtype=torch.uint32, device="cuda")
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(reps)]
+        for e0, e1 in evs:
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+        torch.cuda.synchronize()
+        return min(e0.elapsed_time(e1) for e0, e1 in evs)
+
+    out = {"workload": "exp dir [1,1+2^-13) 2^39 args, eps 2^-32, N = 2^15: 2^24 pieces",
+           "pieces": n}
+    for name, alg in (("lefevre_alg3", _lib.HR_FILTER_LEFEVRE),
+                      ("regular_alg4", _lib.HR_FILTER_REGULAR)):
+        ms = timed(lambda: _lib.hr_filter(ctx, alg, a, b, N, lo, d, n, passed, None, iters,
+                                          stream))
+        it = iters.cpu().numpy()
+        w64, w32 = wave_stats(it, 64), wave_stats(it, 32)
+        out[name] = {"kernel_ms": ms, "iters_min": w64["min"], "iters_max": w64["max"],
+                     "iters_mean": w64["mean"], "nmdm_wave64": w64["nmdm"],
+                     "nmdm_32_lanes": w32["nmdm"],
+                     "certified_frac": float(passed.cpu().numpy().mean())}
+    steps = torch.empty(n, dtype=torch.uint32, device="cuda")
+    _lib.hr_search_steps(ctx, a, b, N, lo, d, n, steps, stream)
+    st = steps.cpu().numpy()
+    counts = torch.empty(n, dtype=torch.uint32, device="cuda")
+    offsets = torch.empty(n, dtype=torch.uint64, device="cuda")
+    cap = 1 << 24
+    hits = torch.empty(cap, dtype=torch.uint32, device="cuda")
+    total = torch.zeros(1, dtype=torch.uint64, device="cuda")
+    ms = timed(lambda: _lib.hr_search(ctx, a, b, N, lo, d, n, counts, offsets, hits, None, cap,
+                                      total, stream))
+    w64, w32 = wave_stats(st, 64), wave_stats(st, 32)
+    out["exact_walk"] = {"kernel_ms": ms, "quotients_min": w64["min"], "quotients_max": w64["max"],
+                         "quotients_mean": w64["mean"], "nmdm_wave64": w64["nmdm"],
+                         "nmdm_32_lanes": w32["nmdm"],
+                         "pieces_without_candidates_frac": float(
+                             (counts.cpu().numpy() == 0).mean()),
+                         "candidates": int(total.cpu().numpy()[0])}
+    out["paper_table4"] = {"lefevre": {"min": 5, "max": 328, "mean": 24, "nmdm": 0.256},
+                           "lefevre_specific_instructions": {"min": 5, "max": 31, "mean": 16,
+                                                             "nmdm": 0.257},
+                           "regular": {"min": 8, "max": 19, "mean": 12, "nmdm": 0.001},
+                           "hardware": "Fermi C2070, 32-thread warps"}
+    return out
+
+
+def bench_cpu_simd(step, ctx, stream):
+    """The multi-core SIMD CPU search (libhrcpu.so: AVX-512 regular test,
+    exact walk for the instances it does not certify) on the host cores,
+    over the same 2^22 pieces of the 2^40 slice (tabulated on the device and
+    copied to the host) and over the plain search workload; a stronger CPU
+    comparison than the oracle, which is not tuned."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1211_3056_amd import _cpu, _lib
+    sp = step.spec
+    n = sp.n_sub * sp.tau
+    a = torch.empty(n, dtype=torch.uint64, device="cuda")
+    b = torch.empty(n, dtype=torch.uint64, device="cuda")
+    _lib.hr_tabulate(ctx, step.table, sp.n_sub, sp.delta, sp.tau, sp.W, a, b, stream)
+    torch.cuda.synchronize()
+    A, B = a.cpu().numpy(), b.cpu().numpy()
+    N = np.full(n, sp.N, np.uint32)
+    lo, d = int(step.Pu.win[0]), int(step.Pu.win[1])
+    t0 = time.perf_counter()
+    counts, _, hits = _cpu.search(A, B, N, d, lo=lo, cap=1 << 25)
+    t = time.perf_counter() - t0
+    A1, B1, N1, D1 = synth.config1()
+    t1 = time.perf_counter()
+    c1, _, h1 = _cpu.search(A1, B1, N1, D1)
+    t1 = time.perf_counter() - t1
+    return {"simd_width": _cpu.simd_width(), "threads": os.cpu_count(),
+            "slice_2^40_search_s": t, "slice_2^40_args_per_s": sp.count / t,
+            "slice_2^40_candidates": int(len(hits)),
+            "config1_s": t1, "config1_args_per_s": len(A1) * int(N1[0]) / t1,
+            "config1_hits": int(len(h1)),
+            "note": "degree-1 search only (tabulation and recheck not included)"}
 
 
 def bench_config1(ctx, stream, steps):

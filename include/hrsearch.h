@@ -296,6 +296,30 @@ hr_status hr_subtables(hr_ctx* ctx, const uint64_t* upper, uint32_t upper_degree
                        void* stream);
 
 /*
+ * hr_filter -- the paper's Boolean lower-bound tests of the degree-1
+ * question (Sec. 4), for comparison with the exact search on the device.
+ *
+ * For each instance i (arguments as hr_search: window start lo and width d
+ * shared by `group` consecutive instances), with b' = b - lo:
+ *  alg = HR_FILTER_LEFEVRE: Lefevre's test, Alg. 1 in the swap form of
+ *        Alg. 3 (Sec. 4.1, Sec. 4.3.3);
+ *  alg = HR_FILTER_REGULAR: the regular test unrolled, Alg. 4 (Sec. 4.2-4.3;
+ *        counter updates as Eq. 3 requires),
+ * each computing a lower bound of min_{k < N[i]} (b' - k a) mod 2^64.
+ *  pass   uint8[n]  out: 1 = certified: no k < N[i] is a hit; 0 = not
+ *                   certified (the instance may or may not have hits)
+ *  d_out  uint64[n] out (may be NULL): the distance value at the test's exit
+ *  iters  uint32[n] out (may be NULL): main-loop passes
+ * Errors: HR_EINVAL for an unknown alg, n > 2^32 - 1, group == 0 or a null
+ * required pointer.
+ */
+#define HR_FILTER_LEFEVRE 1
+#define HR_FILTER_REGULAR 2
+hr_status hr_filter(hr_ctx* ctx, int alg, const uint64_t* a, const uint64_t* b, const uint32_t* N,
+                    uint64_t n, const uint64_t* win_lo, const uint64_t* win_d, uint32_t group,
+                    uint8_t* pass, uint64_t* d_out, uint32_t* iters, void* stream);
+
+/*
  * hr_search_steps -- diagnostic: steps[i] = number of partial quotients the
  * closest-point walk of hr_search computes for instance i (arguments as
  * hr_search; 0 where N[i] = 0, the window is empty, a = 0 or N[i] = 1).

@@ -46,7 +46,8 @@ RESULT_BYTES = ctypes.sizeof(hr_result)
 ITEM_BYTES = ctypes.sizeof(hr_item)
 EXPORTS = ("hr_abi_version", "hr_status_str", "hr_create", "hr_destroy", "hr_search", "hr_batch_run",
            "hr_tabulate", "hr_recheck", "hr_pipeline", "hr_quot_check", "hr_subtables",
-           "hr_search_static", "hr_search_steps")
+           "hr_search_static", "hr_search_steps", "hr_filter")
+HR_FILTER_LEFEVRE, HR_FILTER_REGULAR = 1, 2
 
 
 def lib():
@@ -70,6 +71,8 @@ def lib():
     L.hr_search.argtypes = [P, P, P, P, u64, P, P, u32, P, P, P, P, u64, P, P]
     L.hr_search_static.restype = i32
     L.hr_search_static.argtypes = [P, P, P, P, u64, P, P, u32, P, P, P, P, u64, P, P]
+    L.hr_filter.restype = i32
+    L.hr_filter.argtypes = [P, i32, P, P, P, u64, P, P, u32, P, P, P, P]
     L.hr_search_steps.restype = i32
     L.hr_search_steps.argtypes = [P, P, P, P, u64, P, P, u32, P, P]
     L.hr_tabulate.restype = i32
@@ -146,6 +149,13 @@ def hr_search_static(ctx, a, b, N, win_lo, win_d, group, counts, offsets, hits, 
     _check("hr_search_static", lib().hr_search_static(
         ctx.handle, _p(a), _p(b), _p(N), a.numel(), _p(win_lo), _p(win_d), group, _p(counts),
         _p(offsets), _p(hits), _p(hit_inst), cap, _p(total), _stream(stream)))
+
+
+def hr_filter(ctx, alg, a, b, N, win_lo, win_d, group, passed, d_out=None, iters=None,
+              stream=None):
+    _check("hr_filter", lib().hr_filter(ctx.handle, alg, _p(a), _p(b), _p(N), a.numel(),
+                                        _p(win_lo), _p(win_d), group, _p(passed), _p(d_out),
+                                        _p(iters), _stream(stream)))
 
 
 def hr_search_steps(ctx, a, b, N, win_lo, win_d, group, steps, stream=None):

@@ -336,6 +336,127 @@ HR_HD uint64_t search_one(uint64_t a, uint64_t b, uint32_t n, uint64_t D,
 }
 
 // ----------------------------------------------------------------------
+// The paper's lower-bound tests of the degree-1 question (Sec. 4), for
+// measuring them against the exact walk: each returns the distance value d
+// at which it stopped, the number of main-loop passes, and whether it
+// certifies that no k < n has (b - k a) mod 2^64 < D.  Exact 64-bit integer
+// arithmetic; counts saturate at n (only "reaches n" matters).
+
+struct FilterOut {
+    uint64_t d;
+    uint32_t iters;
+    bool success;
+};
+
+HR_HD uint64_t sat_add_mul(uint64_t c, uint64_t k, uint64_t c2, uint64_t n) {
+    // min(c + k c2, n) for c, c2 <= n
+    if (c2 != 0 && k >= n) return n;
+    const unsigned __int128 v = (unsigned __int128)k * c2 + c;
+    return v >= n ? n : (uint64_t)v;
+}
+
+// Lefevre's test (Alg. 1, Sec. 4.1) written with the swap of Alg. 3: the
+// side that is shortened and the other one are picked by selects instead
+// of two mirrored branches.  Lengths start at p = a, q = 1 - a with one
+// interval each; d is b's distance to the closest point on its left.  Per
+// pass: if d >= p a point lands just left of b (d -= p, Failure once
+// d < D) and p is shortened, else q is; the shortened length loses the
+// quotient's multiples of the other (counts grow as in Alg. 1), the test
+// succeeds once the counts reach n, and one subtraction step follows.  A
+// zero length (rational a: the points have become periodic) ends the test
+// with d exact.
+HR_HD FilterOut lefevre_filter(uint64_t a, uint64_t b, uint32_t n, uint64_t D) {
+    FilterOut r{b, 0, false};
+    uint64_t L0 = a, L1 = 0 - a, C0 = 1, C1 = 1, d = b;
+    if (d < D) return r;
+    if (a == 0) {
+        r.success = true;
+        return r;
+    }
+    for (;;) {
+        ++r.iters;
+        const bool p_side = d >= L0;
+        d = p_side ? d - L0 : d;
+        if (p_side && d < D) {
+            r.d = d;
+            return r;
+        }
+        uint64_t x = p_side ? L0 : L1, y = p_side ? L1 : L0;     // x is shortened by y
+        uint64_t cx = p_side ? C0 : C1, cy = p_side ? C1 : C0;
+        if (y == 0) {
+            r.d = d;
+            r.success = d >= D;
+            return r;
+        }
+        const uint64_t k = x / y;
+        x -= k * y;
+        cy = sat_add_mul(cy, k, cx, n);
+        if (cx + cy >= n) {
+            r.d = d;
+            r.success = true;
+            return r;
+        }
+        y -= x;
+        cx = cx + cy >= n ? n : cx + cy;
+        L0 = p_side ? x : y;
+        L1 = p_side ? y : x;
+        C0 = p_side ? cx : cy;
+        C1 = p_side ? cy : cx;
+    }
+}
+
+// The regular test unrolled by two partial quotients (Alg. 4, Sec. 4.3, as
+// Alg. 2 with the counter updates read as in Eq. 3): from p = a, q = 1 and
+// one interval, q then p is shortened by a whole division each pass; d
+// follows b's interval (mod p after q shrinks; after p shrinks, (d - p) mod q
+// when b lies beyond the new p).  The result is read once the counts reach
+// n, or when a length reaches zero.  The first quotient divides 2^64, which
+// does not fit: floor(2^64 / a) and 2^64 mod a are formed from 2^64 - 1.
+HR_HD FilterOut regular_filter(uint64_t a, uint64_t b, uint32_t n, uint64_t D) {
+    FilterOut r{b, 0, false};
+    uint64_t L0 = a, L1 = 0, C0 = 1, C1 = 0, d = b;
+    bool first = true;                  // L1 stands for 2^64
+    bool q_turn = true;
+    for (;;) {
+        if ((q_turn ? L0 : L1) == 0) {
+            r.d = d;
+            r.success = d >= D;
+            return r;
+        }
+        r.iters += q_turn ? 1u : 0u;
+        if (q_turn) {
+            uint64_t k, rem;
+            if (first) {
+                k = ~0ull / L0;
+                rem = ~0ull % L0 + 1;
+                if (rem == L0) {
+                    ++k;
+                    rem = 0;
+                }
+                first = false;
+            } else {
+                k = L1 / L0;
+                rem = L1 - k * L0;
+            }
+            L1 = rem;
+            C1 = sat_add_mul(C1, k, C0, n);
+            d = d % L0;
+        } else {
+            const uint64_t k = L0 / L1;
+            L0 -= k * L1;
+            C0 = sat_add_mul(C0, k, C1, n);
+            d = d >= L0 ? (d - L0) % L1 : d;
+        }
+        if (C0 + C1 >= n) {
+            r.d = d;
+            r.success = d >= D;
+            return r;
+        }
+        q_turn = !q_turn;
+    }
+}
+
+// ----------------------------------------------------------------------
 // Multi-word fixed point: L little-endian 32-bit limbs, value mod 2^(32 L).
 
 template <int L>

@@ -10,6 +10,8 @@
 //   k_items                                          the same over work items
 //                                                    (batched, persistent)
 //   k_zero_u32, k_stats_flush                        counters
+//   k_filter                                         the paper's lower-bound
+//                                                    tests (Alg. 1/3, Alg. 4)
 //   k_search_steps, k_quot_check                     diagnostics
 //
 // Every kernel maps one lane to one independent unit of work (an instance,
@@ -879,14 +881,30 @@ __device__ __forceinline__ void row_full_to_stride(hr::Word<L>* v) {
 }
 
 // One wave: a range of 64 nu consecutive pieces of one sub-interval, lane
-// l taking pieces l, l + 64, .., l + 64 (nu - 1) of it.  Each lane starts
-// from the step-1 difference vectors of rows 0 and 1 at its first piece
-// (straightforward shift, Sec. 5.2), turns them into differences with step
-// 64 (the same conversion as the fused pass), and then advances by one
-// tabulated-difference step per piece (Fig. 7).  At every step the 64 lanes
-// hold 64 consecutive pieces, so each a[] and b[] store of the wave is one
-// contiguous, line-aligned 512-byte run: no staging, no barrier, and no
-// partial cache lines.
+// l taking pieces l, l + 64, .., l + 64 (nu - 1) of it.  Row 0 (giving b)
+// and then row 1 (giving a) are each started from the sub-interval's table
+// at the lane's first piece (straightforward shift, Sec. 5.2), turned into
+// differences with step 64, and advanced by one tabulated-difference step
+// per piece (Fig. 7).  At every step the 64 lanes hold 64 consecutive
+// pieces, so each store of the wave is one contiguous, line-aligned
+// 512-byte run; one row at a time keeps the kernel's registers low.
+template <int L, int DEG, int J>
+__device__ __forceinline__ void tabulate_row(const uint64_t* __restrict__ T, uint64_t i0,
+                                             uint32_t cnt, uint64_t* __restrict__ dst) {
+    constexpr int LEN = DEG + 1 - J;
+    hr::Word<L> v[LEN];
+    {
+        uint32_t cb[DEG][4];
+        binom_limbs<DEG>(i0, cb);
+        row_start<L, DEG, J>(T, cb, v);
+    }
+    row_full_to_stride<L, LEN>(v);
+    for (uint32_t s = 0; s < cnt; ++s) {
+        dst[(uint64_t)kStride * s] = J == 0 ? top64(v[0]) : neg_top64(v[0]);
+        row_step<L, LEN>(v);
+    }
+}
+
 template <int L, int DEG>
 __global__ __launch_bounds__(64) void k_tabulate(const uint64_t* __restrict__ table,
                                                  uint32_t tau, uint32_t nu, uint32_t wps,
@@ -898,23 +916,8 @@ __global__ __launch_bounds__(64) void k_tabulate(const uint64_t* __restrict__ ta
     if (i0 >= tau) return;
     const uint32_t cnt = (uint32_t)hr::umin(nu, (tau - i0 + kStride - 1) / kStride);
     const uint64_t* T = table + sub * n_entries(DEG) * (L / 2);
-    hr::Word<L> v0[DEG + 1], v1[DEG];
-    {
-        uint32_t cb[DEG][4];
-        binom_limbs<DEG>(i0, cb);
-        row_start<L, DEG, 0>(T, cb, v0);
-        row_start<L, DEG, 1>(T, cb, v1);
-    }
-    row_full_to_stride<L, DEG + 1>(v0);
-    row_full_to_stride<L, DEG>(v1);
-    uint64_t* pa = a_out + sub * tau + i0;
-    uint64_t* pb = b_out + sub * tau + i0;
-    for (uint32_t s = 0; s < cnt; ++s) {
-        pb[(uint64_t)kStride * s] = top64(v0[0]);
-        pa[(uint64_t)kStride * s] = neg_top64(v1[0]);
-        row_step<L, DEG + 1>(v0);
-        row_step<L, DEG>(v1);
-    }
+    tabulate_row<L, DEG, 0>(T, i0, cnt, b_out + sub * tau + i0);
+    tabulate_row<L, DEG, 1>(T, i0, cnt, a_out + sub * tau + i0);
 }
 
 // Statistics are summed per wave, then added into one of kStatSlots
@@ -1074,6 +1077,27 @@ __global__ __launch_bounds__(64) void k_stats_flush(unsigned long long* __restri
         for (int f = 0; f < kStatFields; ++f)
             if (v[f]) atomicAdd(stats + f, (unsigned long long)v[f]);
     }
+}
+
+// The paper's lower-bound tests (Lefevre's with swap, Alg. 1/3; the regular
+// one unrolled, Alg. 4) over degree-1 instances, one lane each: pass[i] = 1
+// when the test certifies that instance i has no hit, d_out and iters the
+// distance value and main-loop passes at its exit.
+template <int ALG>
+__global__ __launch_bounds__(kBlock) void k_filter(
+    const uint64_t* __restrict__ a, const uint64_t* __restrict__ b,
+    const uint32_t* __restrict__ N, uint64_t n, const uint64_t* __restrict__ lo,
+    const uint64_t* __restrict__ d, uint32_t group, uint8_t* __restrict__ pass,
+    uint64_t* __restrict__ d_out, uint32_t* __restrict__ iters) {
+    const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t g = i / group;
+    const uint64_t bb = b[i] - (lo ? lo[g] : 0);
+    const hr::FilterOut r = ALG == HR_FILTER_LEFEVRE ? hr::lefevre_filter(a[i], bb, N[i], d[g])
+                                                     : hr::regular_filter(a[i], bb, N[i], d[g]);
+    pass[i] = r.success ? 1 : 0;
+    if (d_out) d_out[i] = r.d;
+    if (iters) iters[i] = r.iters;
 }
 
 // Partial quotients of each instance's closest-point walk (the work of the
@@ -1492,6 +1516,25 @@ hr_status hr_subtables(hr_ctx* ctx, const uint64_t* upper, uint32_t upper_degree
         default: return HR_EINVAL;
     }
 #undef HR_SUBTAB
+    return launched();
+}
+
+hr_status hr_filter(hr_ctx* ctx, int alg, const uint64_t* a, const uint64_t* b, const uint32_t* N,
+                    uint64_t n, const uint64_t* win_lo, const uint64_t* win_d, uint32_t group,
+                    uint8_t* pass, uint64_t* d_out, uint32_t* iters, void* stream) {
+    if (!ctx || !win_d || group == 0 || n > 0xffffffffull) return HR_EINVAL;
+    if (alg != HR_FILTER_LEFEVRE && alg != HR_FILTER_REGULAR) return HR_EINVAL;
+    if (n == 0) return HR_OK;
+    if (!a || !b || !N || !pass) return HR_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return HR_EDEVICE;
+    const uint64_t blocks = (n + kBlock - 1) / kBlock;
+    hipStream_t st = as_stream(stream);
+    if (alg == HR_FILTER_LEFEVRE)
+        k_filter<HR_FILTER_LEFEVRE><<<dim3((uint32_t)blocks), dim3(kBlock), 0, st>>>(
+            a, b, N, n, win_lo, win_d, group, pass, d_out, iters);
+    else
+        k_filter<HR_FILTER_REGULAR><<<dim3((uint32_t)blocks), dim3(kBlock), 0, st>>>(
+            a, b, N, n, win_lo, win_d, group, pass, d_out, iters);
     return launched();
 }
 

@@ -72,6 +72,8 @@ def test_header_constants_match_binding():
     text = open(_lib.HEADER).read()
     fill = int(re.search(r"#define HR_WAVES_FILL\s+(0x[0-9a-fA-F]+)u", text).group(1), 16)
     assert fill == _lib.HR_WAVES_FILL
+    assert int(re.search(r"#define HR_FILTER_LEFEVRE (\d+)", text).group(1)) == _lib.HR_FILTER_LEFEVRE
+    assert int(re.search(r"#define HR_FILTER_REGULAR (\d+)", text).group(1)) == _lib.HR_FILTER_REGULAR
     codes = dict(re.findall(r"\b(HR_E[A-Z]+|HR_OK)\s*=\s*(-?\d+)", text))
     assert {k: int(v) for k, v in codes.items()} == {
         "HR_OK": _lib.HR_OK, "HR_EINVAL": _lib.HR_EINVAL, "HR_ECAPACITY": _lib.HR_ECAPACITY,
@@ -179,3 +181,11 @@ def test_each_parameter_check_returns_before_the_device():
     for kw in ({"group": 0}, {"n": 1 << 32}, {"win_d": None}, {"steps": None}):
         assert sps(**kw) == E, kw
     assert sps(n=0) == OK
+
+    def flt(alg=1, n=1, group=1, win_d=p, passed=p):
+        return L.hr_filter(c, alg, p, p, p, n, p, win_d, group, passed, None, None, None)
+    assert flt() == DEV and flt(alg=2) == DEV
+    for kw in ({"alg": 0}, {"alg": 3}, {"group": 0}, {"n": 1 << 32}, {"win_d": None},
+               {"passed": None}):
+        assert flt(**kw) == E, kw
+    assert flt(n=0) == OK
