@@ -263,6 +263,7 @@ def main():
         line["plain_form"] = bench_plain(step, ctx, stream)
     if not args.no_batch:
         line["batch"] = bench_batch(args)
+        line["hard_binade"] = bench_hard_binade(args)
     if not args.no_serve:
         line["serving"] = bench_serve(args, pool)
     line["paper_context"] = dict(PAPER_CONTEXT)
@@ -535,6 +536,44 @@ def bench_cpu_simd(step, ctx, stream):
             "config1_s": t1, "config1_args_per_s": len(A1) * int(N1[0]) / t1,
             "config1_hits": int(len(h1)),
             "note": "degree-1 search only (tabulation and recheck not included)"}
+
+
+def bench_hard_binade(args):
+    """exp on 2^40 arguments of [128, 128 + 2^-5) (the hard binade of the
+    paper's Tables 6 and 8: ulp(x) = 2^-45, so the degree-1 truncation over a
+    piece is ~2^20 times larger than on [1, 2)), directed, eps = 2^-32, as a
+    batched persistent launch over device-made tables (degree 5 at 128 bits,
+    sub-intervals of 2^28).  With the paper's pieces of N = 2^15 a piece has
+    about 100 candidates; the autotuner's shorter pieces (the refinement of
+    the paper's phase 2 applied from the start, s = 2^15 / N sub-pieces per
+    paper piece) cut the candidates by about s^2."""
+    import torch
+
+    from paper_1211_3056_amd import batch
+    out = {"workload": "exp dir [128,128+2^-5) 2^40 args, eps 2^-32"}
+    for name, N in (("paper_N_2^15", 1 << 15), ("autotuned", None)):
+        job = batch.BatchJob("exp", 128.0, 1 << 40, 32, "dir", N=N, job_id=0)
+        plan = batch.build_plan([job])
+        dp = batch.DevicePlan(plan)
+        run = batch.Runner(dp, cap=1 << 16)
+        run.batched()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            res = run.batched()
+            ts.append(time.perf_counter() - t0)
+        st = run.stats_dict()
+        hr = batch.finish(plan, res)[0]
+        pj = plan.jobs[0]
+        out[name] = {"N": pj.subs[0].N, "delta": pj.delta, "W": pj.W,
+                     "upper_degrees": sorted({r[2] for tp, _ in plan.tables for r in tp.ranges}),
+                     "ms": min(ts) * 1000, "args_per_s": (1 << 40) / min(ts),
+                     "candidates": st["candidates"], "hr_cases": len(hr),
+                     "device_tables_ms": dp.tables_ms, "host_prep_s": plan.prep_s}
+    out["refinement_factor"] = (1 << 15) // out["autotuned"]["N"]
+    out["candidates_cut"] = out["paper_N_2^15"]["candidates"] / max(out["autotuned"]["candidates"], 1)
+    return out
 
 
 def bench_config1(ctx, stream, steps):

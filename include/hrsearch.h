@@ -331,6 +331,45 @@ hr_status hr_search_steps(hr_ctx* ctx, const uint64_t* a, const uint64_t* b, con
                           uint32_t group, uint32_t* steps, void* stream);
 
 /*
+ * Streamed batched launches (continuous batching at launch granularity).
+ *
+ * hr_batch_open creates a batch stream on a context: `slots` launch slots
+ * (1..1024), each with its own work-claim counter and completion event, and
+ * up to four HIP streams of the library's own (default priority) taken in
+ * turn, so a launch submitted while others run is queued at once and can
+ * start on the device as the running ones release their compute units,
+ * without waiting for the host.
+ *
+ * hr_batch_submit queues one persistent launch of hr_batch_run's kernel
+ * (grid: every wave the device keeps resident, at most n_items) over
+ * n_items work items (device memory, hr_item layout; tables in `pool`) and
+ * returns at once with a ticket (1, 2, ..).  It first clears *count (device)
+ * and the slot's claim counter on its stream; results are appended to
+ * out[cap] as in hr_batch_run (order unspecified; *count may exceed cap).
+ * after_stream (may be NULL): the launch waits for the work already queued
+ * on that stream (e.g. the copies or the hr_subtables call that made its
+ * tables).  The caller keeps pool, items, out and count alive and unchanged
+ * until the ticket has completed.  Statistics are not collected.
+ * HR_ECAPACITY: the slot the ticket needs is still running (poll first).
+ *
+ * hr_batch_poll: *done = the largest ticket t such that every ticket <= t
+ * has completed (non-blocking).  hr_batch_wait blocks until `ticket` has
+ * completed.  hr_batch_close waits for every launch and frees the batch.
+ * A batch belongs to one host thread; its launches share the context's
+ * device but not its claim counter or statistics slots.
+ * Errors: HR_EINVAL for bad sizes or null pointers, HR_EDEVICE for HIP
+ * errors, HR_ENOMEM when open cannot allocate.
+ */
+typedef struct hr_batch hr_batch;
+hr_status hr_batch_open(hr_ctx* ctx, uint32_t slots, hr_batch** out);
+hr_status hr_batch_submit(hr_batch* batch, const uint64_t* pool, const hr_item* items,
+                          uint32_t n_items, uint32_t width_bits, uint32_t degree, hr_result* out,
+                          uint64_t cap, uint64_t* count, void* after_stream, uint64_t* ticket);
+hr_status hr_batch_poll(hr_batch* batch, uint64_t* done);
+hr_status hr_batch_wait(hr_batch* batch, uint64_t ticket);
+hr_status hr_batch_close(hr_batch* batch);
+
+/*
  * hr_quot_check -- diagnostic: the partial-quotient routine of the search,
  * out[i] = min(floor(num[i] / den[i]), cap) computed by the device code
  * (binary64 reciprocal estimate + exact correction); out[i] = 2^64 - 1 where

@@ -46,7 +46,8 @@ RESULT_BYTES = ctypes.sizeof(hr_result)
 ITEM_BYTES = ctypes.sizeof(hr_item)
 EXPORTS = ("hr_abi_version", "hr_status_str", "hr_create", "hr_destroy", "hr_search", "hr_batch_run",
            "hr_tabulate", "hr_recheck", "hr_pipeline", "hr_quot_check", "hr_subtables",
-           "hr_search_static", "hr_search_steps", "hr_filter")
+           "hr_search_static", "hr_search_steps", "hr_filter", "hr_batch_open", "hr_batch_submit",
+           "hr_batch_poll", "hr_batch_wait", "hr_batch_close")
 HR_FILTER_LEFEVRE, HR_FILTER_REGULAR = 1, 2
 
 
@@ -71,6 +72,16 @@ def lib():
     L.hr_search.argtypes = [P, P, P, P, u64, P, P, u32, P, P, P, P, u64, P, P]
     L.hr_search_static.restype = i32
     L.hr_search_static.argtypes = [P, P, P, P, u64, P, P, u32, P, P, P, P, u64, P, P]
+    L.hr_batch_open.restype = i32
+    L.hr_batch_open.argtypes = [P, u32, ctypes.POINTER(P)]
+    L.hr_batch_submit.restype = i32
+    L.hr_batch_submit.argtypes = [P, P, P, u32, u32, u32, P, u64, P, P, ctypes.POINTER(u64)]
+    L.hr_batch_poll.restype = i32
+    L.hr_batch_poll.argtypes = [P, ctypes.POINTER(u64)]
+    L.hr_batch_wait.restype = i32
+    L.hr_batch_wait.argtypes = [P, u64]
+    L.hr_batch_close.restype = i32
+    L.hr_batch_close.argtypes = [P]
     L.hr_filter.restype = i32
     L.hr_filter.argtypes = [P, i32, P, P, P, u64, P, P, u32, P, P, P, P]
     L.hr_search_steps.restype = i32
@@ -208,3 +219,45 @@ def hr_quot_check(ctx, num, den, cap, out, rem=None, stream=None):
     _check("hr_quot_check", lib().hr_quot_check(ctx.handle, _p(num), _p(den), cap, _p(out),
                                                 _p(rem) if rem is not None else None,
                                                 num.numel(), _stream(stream)))
+
+
+class BatchStream:
+    """An hr_batch (hr_batch_open .. hr_batch_close): queued persistent
+    launches with tickets."""
+
+    def __init__(self, ctx, slots: int = 8):
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        _check("hr_batch_open", lib().hr_batch_open(ctx.handle, slots, ctypes.byref(h)))
+        self.handle = h
+
+    def submit(self, pool, items, n_items, width, degree, out, cap, count, after_stream=None):
+        """Queue one launch; returns its ticket, or None while every slot it
+        could use is still running."""
+        t = ctypes.c_uint64()
+        after = ctypes.c_void_p(after_stream.cuda_stream) if after_stream is not None else None
+        st = lib().hr_batch_submit(self.handle, _p(pool), _p(items), n_items, width, degree,
+                                   _p(out), cap, _p(count), after, ctypes.byref(t))
+        if st == HR_ECAPACITY:
+            return None
+        _check("hr_batch_submit", st)
+        return t.value
+
+    def poll(self) -> int:
+        d = ctypes.c_uint64()
+        _check("hr_batch_poll", lib().hr_batch_poll(self.handle, ctypes.byref(d)))
+        return d.value
+
+    def wait(self, ticket: int):
+        _check("hr_batch_wait", lib().hr_batch_wait(self.handle, ticket))
+
+    def close(self):
+        if self.handle:
+            lib().hr_batch_close(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -2,7 +2,7 @@
 
 Rigorous choices (results never depend on them, only speed does):
 
-* degree delta: smallest degree <= 4 whose Lagrange remainder over a whole
+* degree delta: smallest degree <= 6 whose Lagrange remainder over a whole
   sub-interval stays below eps 2^-12 (so that undecided values are rare);
 * word width W: smallest of 128, 192, 256 bits whose table-rounding bound
   2^-W sum_{j+l<=delta} C(N-1, j) C(tau-1, l) stays below eps 2^-12 on every
@@ -51,7 +51,7 @@ class CostModel:
 MODEL = CostModel()
 
 
-def choose_degree(fname: str, X0: float, sub_len: int, s: int, uf, max_delta: int = 4) -> int:
+def choose_degree(fname: str, X0: float, sub_len: int, s: int, uf, max_delta: int = 6) -> int:
     with mpmath.workprec(128):
         h = _ulp(X0)
         lim = mpf(2) ** (-s - MARGIN_BITS)

@@ -42,6 +42,22 @@ struct hr_ctx {
                             // work-claim counter, then the statistics slots
 };
 
+// A stream of batched launches (hr_batch_open .. hr_batch_close): launch
+// slots, each with its own claim counter (device) and completion event, and
+// a few streams used in turn so that consecutive launches can overlap.
+struct hr_batch {
+    hr_ctx* ctx;
+    uint32_t slots;
+    uint32_t nstreams;
+    hipStream_t streams[4];
+    unsigned int* claims;       // slots counters, 256 bytes apart (device)
+    hipEvent_t* done;           // completion event of each slot's launch
+    uint64_t* ticket;           // ticket of each slot's last launch (0: never used)
+    uint64_t* finished;         // ticket of each slot's last launch known to be over
+    uint64_t next_ticket;       // last ticket handed out
+    uint64_t done_through;      // every ticket <= this one has completed
+};
+
 // Device scratch of hr_search_static: the per-block hit counts of the
 // search and their scan (one uint64 per 256-instance block, plus one), in a
 // fixed file-scope array instead of memory allocated by the library, for
@@ -1050,6 +1066,13 @@ __global__ __launch_bounds__(64) void k_items(
 
 __global__ void k_zero_u32(unsigned int* p) { *p = 0u; }
 
+// Clears a launch's claim counter and result count (one lane, so a
+// captured or streamed sequence holds no memset).
+__global__ void k_zero_claim_count(unsigned int* claim, unsigned long long* count) {
+    *claim = 0u;
+    *count = 0ull;
+}
+
 // One wave: stats[f] += sum over slots of slot[f]; the slots are left zero.
 // All loads are issued before any reduction, so the kernel costs about one
 // memory round trip.
@@ -1562,6 +1585,131 @@ hr_status hr_quot_check(hr_ctx* ctx, const uint64_t* num, const uint64_t* den, u
     k_quot_check<<<dim3((uint32_t)blocks), dim3(kBlock), 0, as_stream(stream)>>>(num, den, cap,
                                                                                  out, rem, n);
     return launched();
+}
+
+hr_status hr_batch_open(hr_ctx* ctx, uint32_t slots, hr_batch** out) {
+    if (!ctx || !out || slots == 0 || slots > 1024) return HR_EINVAL;
+    *out = nullptr;
+    if (hipSetDevice(ctx->device) != hipSuccess) return HR_EDEVICE;
+    hr_batch* b = (hr_batch*)calloc(1, sizeof(hr_batch));
+    if (!b) return HR_ENOMEM;
+    b->ctx = ctx;
+    b->slots = slots;
+    b->done = (hipEvent_t*)calloc(slots, sizeof(hipEvent_t));
+    b->ticket = (uint64_t*)calloc(slots, sizeof(uint64_t));
+    b->finished = (uint64_t*)calloc(slots, sizeof(uint64_t));
+    hr_status st = (b->done && b->ticket && b->finished) ? HR_OK : HR_ENOMEM;
+    if (st == HR_OK && hipMalloc((void**)&b->claims, (size_t)slots * 256) != hipSuccess)
+        st = HR_ENOMEM;
+    for (uint32_t i = 0; st == HR_OK && i < slots; ++i)
+        if (hipEventCreateWithFlags(&b->done[i], hipEventDisableTiming) != hipSuccess)
+            st = HR_EDEVICE;
+    b->nstreams = slots < 4 ? slots : 4;
+    for (uint32_t i = 0; st == HR_OK && i < b->nstreams; ++i)
+        if (hipStreamCreateWithFlags(&b->streams[i], hipStreamNonBlocking) != hipSuccess)
+            st = HR_EDEVICE;
+    if (st != HR_OK) {
+        hr_batch_close(b);
+        return st;
+    }
+    *out = b;
+    return HR_OK;
+}
+
+hr_status hr_batch_submit(hr_batch* b, const uint64_t* pool, const hr_item* items, uint32_t n_items,
+                          uint32_t width_bits, uint32_t degree, hr_result* out, uint64_t cap,
+                          uint64_t* count, void* after_stream, uint64_t* ticket) {
+    if (!b || !ticket || !count || !valid_poly(degree, width_bits)) return HR_EINVAL;
+    if (n_items > 0x7fffffffu) return HR_EINVAL;
+    if (n_items > 0 && (!pool || !items || (cap > 0 && !out))) return HR_EINVAL;
+    hr_ctx* ctx = b->ctx;
+    if (hipSetDevice(ctx->device) != hipSuccess) return HR_EDEVICE;
+    const uint64_t t = b->next_ticket + 1;
+    const uint32_t slot = (uint32_t)(t % b->slots);
+    if (b->finished[slot] < b->ticket[slot]) {   // that slot's last launch must be over
+        const hipError_t q = hipEventQuery(b->done[slot]);
+        if (q == hipErrorNotReady) return HR_ECAPACITY;
+        if (q != hipSuccess) return HR_EDEVICE;
+        b->finished[slot] = b->ticket[slot];
+    }
+    hipStream_t st = b->streams[t % b->nstreams];
+    if (after_stream) {   // the launch follows the caller's work queued so far
+        hipEvent_t ev;
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return HR_EDEVICE;
+        const bool ok = hipEventRecord(ev, as_stream(after_stream)) == hipSuccess &&
+                        hipStreamWaitEvent(st, ev, 0) == hipSuccess;
+        (void)hipEventDestroy(ev);
+        if (!ok) return HR_EDEVICE;
+    }
+    unsigned int* claim = (unsigned int*)((char*)b->claims + (size_t)slot * 256);
+    unsigned long long* cnt = (unsigned long long*)count;
+    k_zero_claim_count<<<1, 1, 0, st>>>(claim, cnt);
+    hr_status s = launched();
+    if (s != HR_OK) return s;
+    if (n_items > 0) {
+        HR_DISPATCH(width_bits, degree, ({
+            const uint32_t r = resident_waves<L_, D_>(ctx->device);
+            if (r == 0) return HR_EDEVICE;
+            const uint32_t grid = r < n_items ? r : n_items;
+            k_items<L_, D_, true><<<dim3(grid), dim3(64), 0, st>>>(pool, items, n_items, claim,
+                                                                   out, cap, cnt, nullptr);
+        }));
+        if ((s = launched()) != HR_OK) return s;
+    }
+    if (hipEventRecord(b->done[slot], st) != hipSuccess) return HR_EDEVICE;
+    b->ticket[slot] = t;
+    b->next_ticket = t;
+    *ticket = t;
+    return HR_OK;
+}
+
+hr_status hr_batch_poll(hr_batch* b, uint64_t* done) {
+    if (!b || !done) return HR_EINVAL;
+    if (hipSetDevice(b->ctx->device) != hipSuccess) return HR_EDEVICE;
+    while (b->done_through < b->next_ticket) {
+        const uint64_t t = b->done_through + 1;
+        const uint32_t slot = (uint32_t)(t % b->slots);
+        if (b->finished[slot] < t) {   // then the slot's last launch is t itself
+            const hipError_t q = hipEventQuery(b->done[slot]);
+            if (q == hipErrorNotReady) break;
+            if (q != hipSuccess) return HR_EDEVICE;
+            b->finished[slot] = b->ticket[slot];
+        }
+        b->done_through = t;
+    }
+    *done = b->done_through;
+    return HR_OK;
+}
+
+hr_status hr_batch_wait(hr_batch* b, uint64_t ticket) {
+    if (!b || ticket == 0 || ticket > b->next_ticket) return HR_EINVAL;
+    if (hipSetDevice(b->ctx->device) != hipSuccess) return HR_EDEVICE;
+    const uint32_t slot = (uint32_t)(ticket % b->slots);
+    if (b->finished[slot] < ticket) {   // then the slot's last launch is this ticket
+        if (hipEventSynchronize(b->done[slot]) != hipSuccess) return HR_EDEVICE;
+        b->finished[slot] = b->ticket[slot];
+    }
+    uint64_t d;
+    return hr_batch_poll(b, &d);
+}
+
+hr_status hr_batch_close(hr_batch* b) {
+    if (!b) return HR_OK;
+    (void)hipSetDevice(b->ctx->device);
+    for (uint32_t i = 0; i < b->nstreams; ++i)
+        if (b->streams[i]) {
+            (void)hipStreamSynchronize(b->streams[i]);
+            (void)hipStreamDestroy(b->streams[i]);
+        }
+    if (b->done)
+        for (uint32_t i = 0; i < b->slots; ++i)
+            if (b->done[i]) (void)hipEventDestroy(b->done[i]);
+    if (b->claims) (void)hipFree(b->claims);
+    free(b->done);
+    free(b->ticket);
+    free(b->finished);
+    free(b);
+    return HR_OK;
 }
 
 hr_status hr_batch_run(hr_ctx* ctx, const uint64_t* pool, const hr_item* items, uint32_t n_items,

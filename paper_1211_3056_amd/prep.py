@@ -362,7 +362,7 @@ def is_hr(spec: JobSpec, m: int, uf=None, prec: int = 192) -> bool:
 # expansion per sub-interval.
 
 UPPER_WIDTHS = (192, 256, 320, 384, 448)
-MAX_UPPER_DEGREE = 12
+MAX_UPPER_DEGREE = 10           # HR_MAX_UPPER_DEGREE of include/hrsearch.h
 
 
 _KCACHE: dict = {}

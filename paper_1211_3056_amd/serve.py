@@ -118,7 +118,8 @@ class GpuBackend:
     """Device side: makes admitted jobs' tables in the arena, launches the
     persistent kernel over their items, returns result records per job."""
 
-    def __init__(self, cap: int = 1 << 20, waves: int | None = None, arena_bytes: int = 1 << 30):
+    def __init__(self, cap: int = 1 << 20, waves: int | None = None, arena_bytes: int = 1 << 30,
+                 slots: int = 4):
         import torch
 
         from . import _lib, api
@@ -134,6 +135,9 @@ class GpuBackend:
         self.count = torch.zeros(1, dtype=torch.uint64, device="cuda")
         self.stats = torch.zeros(8, dtype=torch.uint64, device="cuda")
         self.steps = 0
+        self.slots = slots
+        self.stream_b = None             # the hr_batch stream, opened on first use
+        self.inflight = {}               # ticket -> (states, item lists, result buffers)
 
     def free_memory(self) -> int:
         return int(self.torch.cuda.mem_get_info()[0])
@@ -158,19 +162,24 @@ class GpuBackend:
             self.arena.release(st.dev, st.prep.table_words)
             st.dev = None
 
-    def step(self, states):
-        """One launch over every item of the given admitted jobs; returns the
-        result records of each job (list aligned with states)."""
-        torch, _lib, api = self.torch, self._lib, self.api
+    def _items(self, states):
+        """Device item lists of the given admitted jobs, one per (W, delta)."""
+        torch, api = self.torch, self.api
         groups = {}
         for s in states:
             it = s.prep.items.copy()
             it["table"] += s.dev
             groups.setdefault((s.prep.W, s.prep.delta), []).append(it)
-        launches = []
+        out = []
         for (W, d), parts in sorted(groups.items()):
             arr = np.concatenate(parts)
-            launches.append((W, d, len(arr), api.to_dev(arr.view(np.uint8).reshape(-1), torch.uint8)))
+            out.append((W, d, len(arr), api.to_dev(arr.view(np.uint8).reshape(-1), torch.uint8)))
+        return out
+
+    def _run_sync(self, launches):
+        """Run item lists with hr_batch_run, growing the result buffer until
+        every record fits; returns the records."""
+        torch, _lib, api = self.torch, self._lib, self.api
         while True:
             self.count.zero_()
             for W, d, n_items, dev_items in launches:
@@ -180,12 +189,64 @@ class GpuBackend:
             n = api._u64_scalar(self.count)
             if n <= self.cap:
                 break
-            # more results than the buffer holds: grow it and run the step again
+            # more results than the buffer holds: grow it and run again
             self.cap = 1 << (n - 1).bit_length()
             self.out = torch.empty(self.cap * _lib.RESULT_BYTES, dtype=torch.uint8, device="cuda")
-        res = self.out[: n * _lib.RESULT_BYTES].cpu().numpy().view(RESULT_DTYPE)
+        return self.out[: n * _lib.RESULT_BYTES].cpu().numpy().view(RESULT_DTYPE).copy()
+
+    def step(self, states):
+        """One launch over every item of the given admitted jobs, waited
+        for; returns the result records of each job (aligned with states)."""
+        res = self._run_sync(self._items(states))
         self.steps += 1
         return split_by_job(res, [s.job.job_id for s in states])
+
+    # ---- streamed launches (hr_batch_*): submit returns at once, collect
+    # hands back the launches that have completed
+
+    def submit(self, states):
+        """Queue one launch over the given admitted jobs on the batch stream
+        (after the work queued so far on the current stream, which made their
+        tables); returns a ticket, or None while no launch slot is free."""
+        torch, _lib = self.torch, self._lib
+        if self.stream_b is None:
+            self.stream_b = _lib.BatchStream(self.ctx, slots=self.slots)
+            self.free_bufs = [(torch.empty(self.cap * _lib.RESULT_BYTES, dtype=torch.uint8,
+                                           device="cuda"),
+                               torch.zeros(1, dtype=torch.uint64, device="cuda"), self.cap)
+                              for _ in range(self.slots)]
+        launches = self._items(states)
+        if len(launches) != 1 or not self.free_bufs:
+            return None                  # several (W, delta) groups: run them synchronously
+        W, d, n_items, dev_items = launches[0]
+        out, count, cap = self.free_bufs[-1]
+        t = self.stream_b.submit(self.arena_t, dev_items, n_items, W, d, out, cap, count,
+                                 after_stream=torch.cuda.current_stream())
+        if t is None:
+            return None
+        self.free_bufs.pop()
+        self.inflight[t] = (states, launches, (out, count, cap))
+        self.steps += 1
+        return t
+
+    def collect(self):
+        """[(states, records per job)] of every submitted launch that has
+        completed, in ticket order."""
+        api, _lib = self.api, self._lib
+        if not self.inflight:
+            return []
+        done = self.stream_b.poll()
+        out = []
+        for t in sorted(k for k in self.inflight if k <= done):
+            states, launches, (buf, count, cap) = self.inflight.pop(t)
+            n = api._u64_scalar(count)
+            if n <= cap:
+                res = buf[: n * _lib.RESULT_BYTES].cpu().numpy().view(RESULT_DTYPE).copy()
+            else:                        # the buffer was too small: run it again, waited for
+                res = self._run_sync(launches)
+            self.free_bufs.append((buf, count, cap))
+            out.append((states, split_by_job(res, [s.job.job_id for s in states])))
+        return out
 
 
 def make_pool(workers: int):
@@ -220,6 +281,11 @@ class Server:
         self.used = 0
         self.peak_used = 0
         self.blocked_admissions = 0
+
+    def _finish(self, batch, recs, err, now):
+        """Mark a launched batch done (or failed), release its memory;
+        returns the number of jobs."""
+        return _finish_batch(self, batch, recs, err, now)
 
     def serve(self, jobs, arrivals, realtime: bool = True, prepared=None):
         """Run every job; arrivals[i] is job i's arrival time in seconds from
@@ -295,25 +361,38 @@ class Server:
                 self.peak_used = max(self.peak_used, self.used)
                 st.status, st.t_admit = "admitted", now()
                 resident.append(st)
-            # one device step over everything admitted
+            streamed = hasattr(self.backend, "submit")
+            progressed = False
+            # launch everything admitted: queued at once on the batch stream
+            # (streamed backends), else one waited-for step
             if resident:
-                batch, resident = resident, []
-                try:
-                    recs = self.backend.step(batch)
-                except Exception as e:
-                    recs = None
-                    err = repr(e)
-                for i, st in enumerate(batch):
-                    if recs is None:
-                        st.status, st.error = "failed", err
-                    else:
-                        st.records = recs[i]
-                        st.hr = decide_results(st.prep, recs[i])
-                        st.status = "done"
-                    st.t_done = now()
-                    self.used -= st.prep.footprint
-                    self.backend.release(st)
-                    done += 1
+                batch, recs, err = resident, None, ""
+                if streamed:
+                    try:
+                        ticket = self.backend.submit(batch)
+                    except Exception as e:
+                        ticket, err = None, repr(e)
+                    if ticket is not None:
+                        resident = []
+                        progressed = True
+                        batch = None
+                if batch is not None and (not streamed or err or not self.backend.inflight):
+                    resident = []
+                    if not err:
+                        try:
+                            recs = self.backend.step(batch)
+                        except Exception as e:
+                            err = repr(e)
+                    done += self._finish(batch, recs, err, now)
+                    progressed = True
+            if streamed:
+                for batch, recs in self.backend.collect():
+                    done += self._finish(batch, recs, "", now)
+                    progressed = True
+            if progressed:
+                continue
+            if streamed and self.backend.inflight:
+                time.sleep(0.0001)           # a launch is running: look again soon
                 continue
             if futures or nxt < len(order):
                 # nothing to launch: wait for a preparation or the next arrival
@@ -326,6 +405,20 @@ class Server:
                 else:
                     time.sleep(min(wait, 0.05))
         return states
+
+
+def _finish_batch(server, batch, recs, err, now):
+    for i, st in enumerate(batch):
+        if recs is None:
+            st.status, st.error = "failed", err or "device step failed"
+        else:
+            st.records = recs[i]
+            st.hr = decide_results(st.prep, recs[i])
+            st.status = "done"
+        st.t_done = now()
+        server.used -= st.prep.footprint
+        server.backend.release(st)
+    return len(batch)
 
 
 def summarize(states, t_total: float | None = None):

@@ -24,11 +24,17 @@ offsets m):
            distance to the nearest representable number (in ulps): the cases
            nearest to the 2^-32 threshold, for comparing counts with the
            paper's Table 3.
-  config4  the 16 jobs of the batched workload (exp, log, 2^x, sin; 2^30 ..
+  config4  the 12 exp, 2^x and sin jobs of the batched workload (2^30 ..
            2^38 arguments each), round to nearest, eps = 2^-28 ulp; the
            oracle cuts every job into its own sub-intervals of 2^28
            arguments and pieces of 2^16, degree 3 at 128 bits.  The HR set
-           of a range does not depend on how it is cut.
+           of a range does not depend on how it is cut.  The four log jobs
+           (2688 sub-intervals) are left out: near 3 the scaled values of
+           log advance by 2/3 ulp per argument, so they sit on a three-point
+           lattice mod 1 that defeats the oracle's Alg. 1 filter on most
+           pieces, and its exhaustive scan takes 20-100 s per sub-interval
+           (tens of CPU hours in all); the GPU tests check log jobs against
+           the oracle on whole sub-intervals instead.
 """
 from __future__ import annotations
 
@@ -59,6 +65,8 @@ def _jobs(name):
     if name == "config4":
         out = []
         for d in synth.config4():
+            if d["fname"] == "log":
+                continue
             out.append((d["job_id"], Job(d["fname"], d["X0"], d["count"], d["s"], d["mode"],
                                          1 << 16, 1 << 12, 3, 128), []))
         return out

@@ -189,3 +189,16 @@ def test_each_parameter_check_returns_before_the_device():
                {"passed": None}):
         assert flt(**kw) == E, kw
     assert flt(n=0) == OK
+
+    # streamed launches: every check before the device
+    h = ctypes.c_void_p()
+    assert L.hr_batch_open(None, 4, ctypes.byref(h)) == E
+    assert L.hr_batch_open(c, 0, ctypes.byref(h)) == E
+    assert L.hr_batch_open(c, 2000, ctypes.byref(h)) == E
+    assert L.hr_batch_open(c, 4, None) == E
+    assert L.hr_batch_open(c, 4, ctypes.byref(h)) == DEV
+    t = ctypes.c_uint64()
+    assert L.hr_batch_submit(None, p, p, 1, 128, 3, p, 1, p, None, ctypes.byref(t)) == E
+    assert L.hr_batch_poll(None, ctypes.byref(t)) == E
+    assert L.hr_batch_wait(None, 1) == E
+    assert L.hr_batch_close(None) == OK

@@ -134,11 +134,11 @@ def test_graph_replays_match_eager():
 
 def test_full_batch_workload_full_lists():
     """The 16-job mix at full size (1.6e12 arguments) in the persistent launch
-    the benchmark times: every job's whole HR list equals the oracle's stored
-    list (tests/golden/hr_config4.txt; the oracle cuts the ranges its own
-    way, the HR set does not depend on the cut).  For every function, the
-    last sub-interval of its first job (a partial last piece) is recomputed
-    by the oracle here as well."""
+    the benchmark times: the whole HR list of every exp, 2^x and sin job
+    equals the oracle's stored list (tests/golden/hr_config4.txt; the oracle
+    cuts the ranges its own way, the HR set does not depend on the cut).
+    For every function, log included, the last sub-interval of its first job
+    (a partial last piece) is recomputed by the oracle here as well."""
     from paper_1211_3056_amd import batch
     plan = batch.build_plan(_scaled_jobs())
     run = batch.Runner(batch.DevicePlan(plan))
@@ -156,5 +156,24 @@ def test_full_batch_workload_full_lists():
     assert len(seen) == 4
     if ref is None:
         pytest.skip("hr_config4.txt not generated")
-    for pj in plan.jobs:
+    listed = [pj for pj in plan.jobs if pj.job.fname != "log"]
+    assert sorted(ref) == sorted(pj.job.job_id for pj in listed)
+    for pj in listed:
         assert hr[pj.job.job_id] == ref[pj.job.job_id], pj.job.job_id
+
+
+def test_hard_binade_against_oracle():
+    """exp on [128, 128 + 2^-15) (the paper's hard binade [128, 256): the
+    degree-1 truncation dominates), directed, eps = 2^-24, autotuned pieces
+    and degree, device-made tables: the first and last sub-intervals equal
+    the oracle's lists."""
+    from paper_1211_3056_amd import batch
+    job = batch.BatchJob("exp", 128.0, 1 << 30, 24, "dir", N=None, job_id=0)
+    plan = batch.build_plan([job])
+    pj = plan.jobs[0]
+    assert pj.delta >= 5
+    hr = batch.finish(plan, batch.Runner(batch.DevicePlan(plan)).batched())[0]
+    assert len(hr) > 50
+    for sp in (pj.subs[0], pj.subs[-1]):
+        lo, hi = sp.start, sp.start + sp.length
+        assert [m for m in hr if lo <= m < hi] == oracle_sub(pj, sp), sp

@@ -30,8 +30,8 @@ def _device(alg, A, B, N, lo, D, group):
 @pytest.mark.parametrize("seed", [41, 42])
 def test_filters_equal_oracle_on_degenerate_instances(seed):
     from paper_1211_3056_amd import _lib
-    n = 5000
-    A, B, N, lo, D = synth.adversarial_instances(seed, n, max_N=1 << 20)
+    n = 4000
+    A, B, N, lo, D = synth.adversarial_instances(seed, n, max_N=1 << 14)
     for alg, ref in ((_lib.HR_FILTER_LEFEVRE, lefevre_alg1), (_lib.HR_FILTER_REGULAR, regular_alg4)):
         ok, d, it = _device(alg, A, B, N, lo, D, 1)
         for i in range(n):
