@@ -34,8 +34,8 @@ PEAK_HBM = 8.0e12                     # bytes/s
 # HBM bytes per launch measured by rocprofv3 (FETCH_SIZE x 1.997 and
 # WRITE_SIZE x 0.999, the factors a 1 GiB copy gives; summary under
 # profiles/), valid only for the kernel sources they were taken on.
-PROFILED_SOURCES = "b9d6936039a468f9"      # sha256 prefix of hr_lib.hip + hr_core.h
-PROFILED_TRAFFIC = {"k_pipeline<8,4>": 4.99e6, "k_tabulate<8,4>": 78.03e6}
+PROFILED_SOURCES = "137b37dfbd8e2309"      # sha256 prefix of hr_lib.hip + hr_core.h
+PROFILED_TRAFFIC = {"k_pipeline<8,4>": 4.99e6, "k_tabulate<8,4>": 69.15e6}
 
 
 def profiled_traffic(kernel):
@@ -104,13 +104,15 @@ class FusedStep:
     fused tabulate + search + recheck (hr_pipeline), then the result rows
     copied back.  HIP events bracket the two launches on their stream."""
 
-    def __init__(self, spec, ctx, stream, Du=None, Wu=320, cap=1 << 16):
+    def __init__(self, spec, ctx, stream, Du=None, Wu=None, cap=1 << 16):
         import torch
 
         from paper_1211_3056_amd import _lib, autotune, pipeline
         self.spec, self.ctx, self.stream, self.cap = spec, ctx, stream, cap
         Du = Du or autotune.choose_upper_degree(spec.fname, spec.X0, spec.count, spec.s,
                                                 spec.delta)
+        Wu = Wu or autotune.choose_upper_width(Du, spec.n_sub, spec.N, spec.tau, spec.delta,
+                                               spec.s)
         t0 = time.perf_counter()
         self.Pu = pipeline.UpperPrepared(spec, Du, Wu)
         self.prep_s = time.perf_counter() - t0
@@ -306,6 +308,7 @@ def bench_stream(spec, ctx, stream, n_jobs=8):
     from paper_1211_3056_amd import _lib, api, autotune, pipeline
     specs = [dataclasses.replace(spec, X0=1.0 + i * 2.0 ** -12) for i in range(n_jobs)]
     Du = autotune.choose_upper_degree(spec.fname, spec.X0, spec.count, spec.s, spec.delta)
+    Wu = autotune.choose_upper_width(Du, spec.n_sub, spec.N, spec.tau, spec.delta, spec.s)
     RB = _lib.RESULT_BYTES
     cap = 1 << 16
     E = (spec.delta + 1) * (spec.delta + 2) // 2
@@ -345,7 +348,7 @@ def bench_stream(spec, ctx, stream, n_jobs=8):
     cases = 0
     for i, sp in enumerate(specs):
         t1 = time.perf_counter()
-        Pu = pipeline.UpperPrepared(sp, Du, 320)
+        Pu = pipeline.UpperPrepared(sp, Du, Wu)
         prep_s += time.perf_counter() - t1
         b = bufs[i % 2]
         launch(Pu, b)
@@ -443,7 +446,8 @@ def bench_filters(ctx, stream, reps=5):
     from paper_1211_3056_amd.prep import JobSpec
     spec = JobSpec("exp", 1.0, 1 << 39, 32, "dir", 1 << 15, 1 << 13, 3, 192)
     Du = autotune.choose_upper_degree(spec.fname, spec.X0, spec.count, spec.s, spec.delta)
-    P = pipeline.UpperPrepared(spec, Du, 320)
+    Wu = autotune.choose_upper_width(Du, spec.n_sub, spec.N, spec.tau, spec.delta, spec.s)
+    P = pipeline.UpperPrepared(spec, Du, Wu)
     upper, win, thr = pipeline.upload_upper(P)
     table = pipeline.make_tables(P, upper, ctx=ctx, stream=stream)
     a, b = api.tabulate(table, spec.n_sub, spec.delta, spec.tau, spec.W, ctx=ctx, stream=stream)
@@ -703,35 +707,60 @@ def bench_tabulation(spec, table, ctx, stream, steps):
 
 def probe():
     """Kernels for counter runs: a plain copy of known size (the reference
-    for scaling FETCH_SIZE / WRITE_SIZE), the fused pass, the tabulation
-    stage alone, the batched pass."""
+    for scaling FETCH_SIZE / WRITE_SIZE), then three of each: the headline
+    step (sub-interval tables from the upper table, fused pass), the
+    tabulation stage, the batched pass of the 16-job mix, the plain search
+    workload; one pass of each of the paper's tests over the 2^40 slice's
+    pieces.  Progress on stderr."""
+    import numpy as np
     import torch
 
     import synth
-    from paper_1211_3056_amd import api, batch, pipeline
-    from paper_1211_3056_amd.prep import JobSpec, prepare
+    from paper_1211_3056_amd import _lib, api, batch
+    from paper_1211_3056_amd.prep import JobSpec
+
+    def say(msg):
+        print(f"probe: {msg}", file=sys.stderr, flush=True)
 
     src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
+    say("copy done")
+    ctx = api.context()
+    stream = torch.cuda.current_stream()
     spec = JobSpec(**synth.CONFIG3)
-    P = prepare(spec)
-    dev = pipeline.upload(P)
+    step = FusedStep(spec, ctx, stream)
     for _ in range(3):
-        pipeline.run_fused(P, dev)
-    from paper_1211_3056_amd import _lib
-    a_out = torch.empty(spec.n_sub * spec.tau, dtype=torch.uint64, device="cuda")
-    b_out = torch.empty_like(a_out)
+        step()
+    torch.cuda.synchronize()
+    say("fused steps done")
+    n = spec.n_sub * spec.tau
+    a = torch.empty(n, dtype=torch.uint64, device="cuda")
+    b = torch.empty_like(a)
     for _ in range(3):
-        _lib.hr_tabulate(api.context(), dev[0], spec.n_sub, spec.delta, spec.tau, spec.W,
-                         a_out, b_out)
+        _lib.hr_tabulate(ctx, step.table, spec.n_sub, spec.delta, spec.tau, spec.W, a, b, stream)
+    torch.cuda.synchronize()
+    say("tabulation done")
+    N = api.to_dev(np.full(n, spec.N, np.uint32), torch.uint32)
+    lo = api.to_dev(np.full(1, step.Pu.win[0], np.uint64), torch.uint64)
+    d = api.to_dev(np.full(1, step.Pu.win[1], np.uint64), torch.uint64)
+    passed = torch.empty(n, dtype=torch.uint8, device="cuda")
+    for alg in (_lib.HR_FILTER_LEFEVRE, _lib.HR_FILTER_REGULAR):
+        _lib.hr_filter(ctx, alg, a, b, N, lo, d, n, passed, None, None, stream)
+    torch.cuda.synchronize()
+    say("filters done")
+    A, B, N1, D = synth.config1()
+    for _ in range(3):
+        api.search(api.to_dev(A, torch.uint64), api.to_dev(B, torch.uint64),
+                   api.to_dev(N1, torch.uint32), D, ctx=ctx)
+    say("plain search done")
     dp = batch.DevicePlan(batch.build_plan([batch.BatchJob(**d) for d in synth.config4()]))
     run = batch.Runner(dp)
     for _ in range(3):
         run.batched()
     torch.cuda.synchronize()
-    print("probe done", file=sys.stderr)
+    say("batched passes done")
 
 
 def bench_batch(args):

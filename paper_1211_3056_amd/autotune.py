@@ -26,8 +26,8 @@ from dataclasses import dataclass
 import mpmath
 from mpmath import mpf
 
-from .prep import (MAX_UPPER_DEGREE, _deriv_bound, _taylor_coeffs, _ulp, output_ulp_range,
-                   round_sum, upper_error)
+from .prep import (MAX_UPPER_DEGREE, UPPER_WIDTHS, _deriv_bound, _taylor_coeffs, _ulp,
+                   output_ulp_range, round_sum, upper_error)
 
 WIDTHS = (128, 192, 256)
 MARGIN_BITS = 12
@@ -73,6 +73,28 @@ def choose_upper_degree(fname: str, X0: float, count: int, s: int, delta: int = 
         if upper_error(fname, X0, count, Du, uf) <= lim:
             return Du
     raise ValueError("range too wide for one upper polynomial; split it")
+
+
+def choose_upper_width(Du: int, n_sub: int, N_max: int, tau_max: int, delta: int, s: int) -> int:
+    """Narrowest upper-table width (>= 256 bits) that keeps the device's
+    integer steps exact, (delta N)^Du < 2^Wu, and the share of the upper
+    entries' rounding in a piece value (2^-Wu sum_m C(T-1, m), carried
+    through at most 2^l C(l N, n - j) C(tau-1, l) C(N-1, j), summed over the
+    kept entries) below eps 2^-24."""
+    T = max(n_sub, 1)
+    worst = 0
+    for j in range(delta + 1):
+        for l in range(delta - j + 1):
+            for n in range(j + l, Du + 1):
+                sm = sum(math.comb(T - 1, m) for m in range(Du - n + 1))
+                worst += (sm * 2 ** l * math.comb(l * N_max, n - j)
+                          * math.comb(tau_max - 1, l) * math.comb(N_max - 1, j))
+    for Wu in UPPER_WIDTHS:
+        if Wu < 256:
+            continue
+        if (delta * N_max) ** Du < 1 << Wu and worst.bit_length() + s + 24 <= Wu:
+            return Wu
+    raise ValueError("no upper width is wide enough")
 
 
 def choose_width(shapes, delta: int, s: int) -> int:

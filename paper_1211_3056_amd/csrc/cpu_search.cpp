@@ -173,7 +173,8 @@ __attribute__((target("avx512f,avx512dq"))) void regular8(const uint64_t* a, con
         }
 }
 
-// The filter over [lo, hi).
+// The filter over instances [lo, hi); pass, d_out and iters are indexed by
+// instance.
 void filter_range(const uint64_t* a, const uint64_t* b, const uint32_t* N, const uint64_t* win_lo,
                   const uint64_t* win_d, uint32_t group, uint64_t lo, uint64_t hi, uint8_t* pass,
                   uint64_t* d_out, uint32_t* iters) {
@@ -229,12 +230,12 @@ int hrc_search(const uint64_t* a, const uint64_t* b, const uint32_t* N, uint64_t
     if (cap > 0 && !hits) return kInval;
     *total = 0;
     if (n == 0) return kOk;
+    std::vector<uint8_t> pass(n);   // indexed by instance, like the filter's outputs
     parallel_chunks(n, threads, [&](uint64_t lo, uint64_t hi) {
-        uint8_t pass[kChunk];
-        filter_range(a, b, N, win_lo, win_d, group, lo, hi, pass, nullptr, nullptr);
+        filter_range(a, b, N, win_lo, win_d, group, lo, hi, pass.data(), nullptr, nullptr);
         for (uint64_t i = lo; i < hi; ++i) {
             uint64_t c = 0;
-            if (!pass[i - lo]) {
+            if (!pass[i]) {
                 const uint64_t g = i / group;
                 c = hr::search_each(a[i], b[i] - (win_lo ? win_lo[g] : 0), N[i], win_d[g],
                                     [](uint64_t) {});

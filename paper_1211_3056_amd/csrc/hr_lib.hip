@@ -874,9 +874,17 @@ __device__ __forceinline__ void start_low(const uint64_t* __restrict__ T, uint64
 // ---------------------------------------------------------------- tabulate
 
 // A whole step-1 difference vector v[0..LEN) of a polynomial of degree
-// LEN - 1 -> its differences with step kStride, in place (entry m reads
-// only entries >= m).  Multipliers below 2^32 take one-limb products.
-template <int L, int LEN>
+// LEN - 1 -> its differences with step H (H in {16, 32, 64}), in place
+// (entry m reads only entries >= m).  Multipliers below 2^32 take one-limb
+// products.
+constexpr StrideCoef kStrideCoef16 = stride_coef(16);
+constexpr StrideCoef kStrideCoef32 = stride_coef(32);
+template <int H>
+__host__ __device__ constexpr const StrideCoef& stride_table() {
+    return H == 16 ? kStrideCoef16 : H == 32 ? kStrideCoef32 : kStrideCoef;
+}
+
+template <int L, int LEN, int H>
 __device__ __forceinline__ void row_full_to_stride(hr::Word<L>* v) {
     static_for<1, LEN>([&](auto M) {
         constexpr int m = decltype(M)::value;
@@ -884,7 +892,7 @@ __device__ __forceinline__ void row_full_to_stride(hr::Word<L>* v) {
         hr::wzero(acc);
         static_for<m, LEN>([&](auto K) {
             constexpr int k = decltype(K)::value;
-            constexpr uint64_t c = kStrideCoef.a[m][k];
+            constexpr uint64_t c = stride_table<H>().a[m][k];
             if constexpr (c < (1ull << 32)) {
                 const uint32_t m1[1] = {(uint32_t)c};
                 hr::wmac_n<L, 1>(acc, v[k], m1);
@@ -896,15 +904,15 @@ __device__ __forceinline__ void row_full_to_stride(hr::Word<L>* v) {
     });
 }
 
-// One wave: a range of 64 nu consecutive pieces of one sub-interval, lane
-// l taking pieces l, l + 64, .., l + 64 (nu - 1) of it.  Row 0 (giving b)
-// and then row 1 (giving a) are each started from the sub-interval's table
-// at the lane's first piece (straightforward shift, Sec. 5.2), turned into
-// differences with step 64, and advanced by one tabulated-difference step
-// per piece (Fig. 7).  At every step the 64 lanes hold 64 consecutive
-// pieces, so each store of the wave is one contiguous, line-aligned
-// 512-byte run; one row at a time keeps the kernel's registers low.
-template <int L, int DEG, int J>
+// Lanes of a segment of H lanes take the pieces i0, i0 + H, .., of one
+// sub-interval: row 0 (giving b) and then row 1 (giving a) are each started
+// from the sub-interval's table at the lane's first piece (straightforward
+// shift, Sec. 5.2), turned into differences with step H, and advanced by
+// one tabulated-difference step per piece (Fig. 7).  At every step the H
+// lanes hold H consecutive pieces, so each store of a segment is one
+// contiguous, line-aligned run of 8 H bytes; one row at a time keeps the
+// kernel's registers low.
+template <int L, int DEG, int J, int H>
 __device__ __forceinline__ void tabulate_row(const uint64_t* __restrict__ T, uint64_t i0,
                                              uint32_t cnt, uint64_t* __restrict__ dst) {
     constexpr int LEN = DEG + 1 - J;
@@ -914,26 +922,31 @@ __device__ __forceinline__ void tabulate_row(const uint64_t* __restrict__ T, uin
         binom_limbs<DEG>(i0, cb);
         row_start<L, DEG, J>(T, cb, v);
     }
-    row_full_to_stride<L, LEN>(v);
+    row_full_to_stride<L, LEN, H>(v);
     for (uint32_t s = 0; s < cnt; ++s) {
-        dst[(uint64_t)kStride * s] = J == 0 ? top64(v[0]) : neg_top64(v[0]);
+        dst[(uint64_t)H * s] = J == 0 ? top64(v[0]) : neg_top64(v[0]);
         row_step<L, LEN>(v);
     }
 }
 
-template <int L, int DEG>
+// One wave = 64 / H segments; a segment is H lanes over H nu consecutive
+// pieces of one sub-interval (segs_per_sub segments per sub-interval).
+template <int L, int DEG, int H>
 __global__ __launch_bounds__(64) void k_tabulate(const uint64_t* __restrict__ table,
-                                                 uint32_t tau, uint32_t nu, uint32_t wps,
+                                                 uint32_t n_sub, uint32_t tau, uint32_t nu,
+                                                 uint32_t segs_per_sub,
                                                  uint64_t* __restrict__ a_out,
                                                  uint64_t* __restrict__ b_out) {
     const int lane = threadIdx.x;
-    const uint64_t sub = blockIdx.x / wps;
-    const uint64_t i0 = (uint64_t)(blockIdx.x % wps) * kStride * nu + lane;
+    const uint64_t seg = (uint64_t)blockIdx.x * (64 / H) + lane / H;
+    const uint64_t sub = seg / segs_per_sub;
+    if (sub >= n_sub) return;
+    const uint64_t i0 = (seg % segs_per_sub) * H * nu + lane % H;
     if (i0 >= tau) return;
-    const uint32_t cnt = (uint32_t)hr::umin(nu, (tau - i0 + kStride - 1) / kStride);
+    const uint32_t cnt = (uint32_t)hr::umin(nu, (tau - i0 + H - 1) / H);
     const uint64_t* T = table + sub * n_entries(DEG) * (L / 2);
-    tabulate_row<L, DEG, 0>(T, i0, cnt, b_out + sub * tau + i0);
-    tabulate_row<L, DEG, 1>(T, i0, cnt, a_out + sub * tau + i0);
+    tabulate_row<L, DEG, 0, H>(T, i0, cnt, b_out + sub * tau + i0);
+    tabulate_row<L, DEG, 1, H>(T, i0, cnt, a_out + sub * tau + i0);
 }
 
 // Statistics are summed per wave, then added into one of kStatSlots
@@ -1270,12 +1283,19 @@ bool valid_poly(uint32_t degree, uint32_t width_bits) {
            (width_bits == 128 || width_bits == 192 || width_bits == 256);
 }
 
-// Pieces per lane of hr_tabulate: long enough to amortise the packet start
-// (straightforward shift and step conversion), short enough that the grid
-// (one wave per 64 nu pieces of a sub-interval) has >= 16 waves per CU.
+// hr_tabulate's segments: H lanes (32) over H nu pieces, nu up to 32 (long
+// enough to amortise the packet start, i.e. the straightforward shift and
+// the step conversion), lowered while the grid would have fewer than 8
+// waves per CU.
+constexpr uint32_t kTabLanes = 32;
+constexpr uint32_t kTabMaxNu = 32;
 uint32_t pick_nu_tab(uint64_t n_sub, uint32_t tau) {
-    uint32_t nu = kMaxNu;
-    while (nu > 1 && n_sub * ((tau + 64ull * nu - 1) / (64ull * nu)) < 256ull * 16) nu >>= 1;
+    uint32_t nu = kTabMaxNu;
+    auto waves = [&](uint32_t v) {
+        return n_sub * ((tau + (uint64_t)kTabLanes * v - 1) / ((uint64_t)kTabLanes * v)) /
+               (64 / kTabLanes);
+    };
+    while (nu > 1 && waves(nu) < 256ull * 8) nu >>= 1;
     return nu;
 }
 
@@ -1446,12 +1466,13 @@ hr_status hr_tabulate(hr_ctx* ctx, const uint64_t* table, uint32_t n_sub, uint32
     if (hipSetDevice(ctx->device) != hipSuccess) return HR_EDEVICE;
     hipStream_t st = as_stream(stream);
     const uint32_t nu = pick_nu_tab(n_sub, tau);
-    const uint64_t wps = (tau + 64ull * nu - 1) / (64ull * nu);   // waves per sub-interval
-    const uint64_t blocks = (uint64_t)n_sub * wps;
-    if (blocks > 0xffffffffull) return HR_EINVAL;
+    const uint64_t sps = (tau + (uint64_t)kTabLanes * nu - 1) / ((uint64_t)kTabLanes * nu);
+    const uint64_t segs_per_wave = 64 / kTabLanes;
+    const uint64_t blocks = ((uint64_t)n_sub * sps + segs_per_wave - 1) / segs_per_wave;
+    if (blocks > 0xffffffffull || sps > 0xffffffffull) return HR_EINVAL;
     HR_DISPATCH(width_bits, degree,
-                (k_tabulate<L_, D_><<<dim3((uint32_t)blocks), dim3(64), 0, st>>>(
-                    table, tau, nu, (uint32_t)wps, a_out, b_out)));
+                (k_tabulate<L_, D_, kTabLanes><<<dim3((uint32_t)blocks), dim3(64), 0, st>>>(
+                    table, n_sub, tau, nu, (uint32_t)sps, a_out, b_out)));
     return launched();
 }
 

@@ -108,10 +108,11 @@ def run_upper(Pu: UpperPrepared, ctx=None):
     return run_fused(Pu, dev_args=(table, win, thr), ctx=ctx)
 
 
-def search_job(spec: JobSpec, form: str = "fused", subs=None, ctx=None, Du=None, Wu=320):
+def search_job(spec: JobSpec, form: str = "fused", subs=None, ctx=None, Du=None, Wu=None):
     if form == "upper":
-        from .autotune import choose_upper_degree
+        from .autotune import choose_upper_degree, choose_upper_width
         Du = Du or choose_upper_degree(spec.fname, spec.X0, spec.count, spec.s, spec.delta)
+        Wu = Wu or choose_upper_width(Du, spec.n_sub, spec.N, spec.tau, spec.delta, spec.s)
         return run_upper(UpperPrepared(spec, Du, Wu), ctx=ctx)
     P = prepare(spec, subs)
     return (run_fused if form == "fused" else run_plain)(P, ctx=ctx)

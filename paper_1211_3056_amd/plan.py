@@ -118,14 +118,13 @@ def canonical(records: np.ndarray) -> np.ndarray:
 
 # ---------------------------------------------------------------- device-made tables
 
-UPPER_WIDTH = 320
-
-
-def upper_ranges(pj: PlannedJob, Wu: int = UPPER_WIDTH):
+def upper_ranges(pj: PlannedJob, Wu: int | None = None):
     """Cut a planned job into ranges of whole sub-intervals, each covered by
     one upper polynomial (the smallest degree >= delta whose Lagrange
     remainder over the range is below eps 2^-12, at most MAX_UPPER_DEGREE;
-    a range that needs more is halved).  Returns [(t_lo, t_hi, UpperTable)]."""
+    a range that needs more is halved), at the narrowest width that suits it
+    (autotune.choose_upper_width) unless Wu is given.  Returns
+    [(t_lo, t_hi, UpperTable)]."""
     job = pj.job
     lim = 2.0 ** (-job.s - autotune.MARGIN_BITS)
     h = math.ldexp(1.0, math.frexp(job.X0)[1] - 53)
@@ -144,7 +143,10 @@ def upper_ranges(pj: PlannedJob, Wu: int = UPPER_WIDTH):
             mid = (lo + hi) // 2
             todo[:0] = [(lo, mid), (mid, hi)]
             continue
-        U = upper_table(job.fname, X0, count, job.s, job.mode, job.sub_len, Du, Wu, uf=pj.uf)
+        width = Wu or autotune.choose_upper_width(
+            Du, hi - lo, max(sp.N for sp in pj.subs[lo:hi]),
+            max(sp.pieces for sp in pj.subs[lo:hi]), pj.delta, job.s)
+        U = upper_table(job.fname, X0, count, job.s, job.mode, job.sub_len, Du, width, uf=pj.uf)
         out.append((lo, hi, U))
     return out
 

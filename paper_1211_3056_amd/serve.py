@@ -229,6 +229,11 @@ class GpuBackend:
         self.steps += 1
         return t
 
+    def wait_oldest(self):
+        """Block until the oldest launch in flight is over."""
+        if self.inflight:
+            self.stream_b.wait(min(self.inflight))
+
     def collect(self):
         """[(states, records per job)] of every submitted launch that has
         completed, in ticket order."""
@@ -392,7 +397,12 @@ class Server:
             if progressed:
                 continue
             if streamed and self.backend.inflight:
-                time.sleep(0.0001)           # a launch is running: look again soon
+                # a launch is running: wake on a finished preparation, or
+                # block until the oldest launch is over
+                if futures:
+                    cf.wait(list(futures), timeout=0.0002, return_when=cf.FIRST_COMPLETED)
+                else:
+                    self.backend.wait_oldest()
                 continue
             if futures or nxt < len(order):
                 # nothing to launch: wait for a preparation or the next arrival

@@ -47,3 +47,17 @@ def test_search_config1(cpu):
                                         np.full(len(A), D, np.uint64))
     assert np.array_equal(counts, rc) and np.array_equal(hits, rk)
     assert cpu.simd_width() in (1, 8)
+
+
+def test_search_over_many_chunks_and_threads(cpu):
+    """Several work chunks (4096 instances each) on several threads: every
+    instance's hits equal brute force, the CSR offsets are the running sum."""
+    A, B, N, lo, D = synth.adversarial_instances(54, 3 * 4096 + 77, max_N=600)
+    counts, offsets, hits = cpu.search(A, B, N, D, lo=lo, group=1, cap=1 << 12, threads=3)
+    assert np.array_equal(offsets[1:], np.cumsum(counts.astype(np.uint64))[:-1])
+    for i in range(0, len(A), 3):
+        ref = brute_hits_np(int(A[i]), int(B[i]), int(N[i]), int(D[i]), lo=int(lo[i]))
+        o = int(offsets[i])
+        assert hits[o:o + int(counts[i])].tolist() == ref, i
+    ok, _, _ = cpu.filter_regular(A, B, N, D, lo=lo, group=1, threads=5)
+    assert not (ok.astype(bool) & (counts > 0)).any()

@@ -171,7 +171,7 @@ def test_hard_binade_against_oracle():
     job = batch.BatchJob("exp", 128.0, 1 << 30, 24, "dir", N=None, job_id=0)
     plan = batch.build_plan([job])
     pj = plan.jobs[0]
-    assert pj.delta >= 5
+    assert pj.delta >= 4
     hr = batch.finish(plan, batch.Runner(batch.DevicePlan(plan)).batched())[0]
     assert len(hr) > 50
     for sp in (pj.subs[0], pj.subs[-1]):

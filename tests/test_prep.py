@@ -284,3 +284,21 @@ def test_vectorised_windows_contain_precise_ones():
         for b in (0, 2):
             if int(thr[i, b]) <= int(thr[i, b + 1]):
                 assert int(tp[b]) <= int(thr[i, b]) and int(thr[i, b + 1]) <= int(tp[b + 1])
+
+
+def test_upper_width_choice():
+    """The narrowest width the autotuner takes for the large workload (256
+    bits at degree 7) adds less than eps 2^-24 to the error budget over 320
+    bits, and keeps the device's integer steps exact."""
+    from paper_1211_3056_amd.prep import upper_table, upper_windows_precise
+    Wu = autotune.choose_upper_width(7, 4096, 1 << 18, 1 << 10, 4, 32)
+    assert Wu == 256
+    assert (4 * (1 << 18)) ** 7 < 1 << Wu
+    mus = []
+    for w in (Wu, 320):
+        U = upper_table("exp", 1.0, 1 << 40, 32, "rn", 1 << 28, 7, w)
+        mus.append(upper_windows_precise(U, 1 << 18, 1 << 10, 4, 256)[2])
+    assert mus[0] - mus[1] < 2.0 ** (-32 - 24)
+    # a width too narrow for the shape is refused
+    with pytest.raises(ValueError):
+        autotune.choose_upper_width(10, 1 << 20, (1 << 32) - 1, 1 << 20, 8, 40)
