@@ -73,6 +73,27 @@ HR_HD uint32_t quot_rem(uint64_t num, const Recip& R, uint32_t cap, uint64_t& re
     return (big || kk >= cap) ? cap : (uint32_t)kk;
 }
 
+// floor(num / den) and the remainder for num < 3 den, by compares and
+// subtractions only.
+HR_HD uint32_t quot_small2(uint64_t num, uint64_t den, uint64_t& rem) {
+    const bool s1 = num >= den;
+    const uint64_t r1 = num - den;
+    const bool s2 = s1 && r1 >= den;
+    rem = s2 ? r1 - den : (s1 ? r1 : num);
+    return (uint32_t)s1 + (uint32_t)s2;
+}
+
+// True when x holds for every active lane of the wave (on the host, for the
+// one caller).  Used only to choose between two exact ways of computing the
+// same values, so the results never depend on it.
+HR_HD bool wave_all(bool x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __ballot(!x) == 0;
+#else
+    return x;
+#endif
+}
+
 HR_HD uint32_t quot_sat(uint64_t num, uint64_t den, uint32_t cap) {
     uint64_t rem;
     return quot_rem(num, recip(den), cap, rem);
@@ -165,13 +186,26 @@ HR_HD void closest_left(uint64_t a, uint64_t b, uint32_t n, Near& r) {
         for (;;) {
             // ---- p > q: p-intervals (left ends < iq) get points at p - q, p - 2q, ..
             ++steps;
-            const Recip Rq = recip(q);
             uint64_t rp;
-            k = quot_rem(p, Rq, n, rp);
             in_x = X < iq;
             // the first new point at or left of b: s = ceil((p - d) / q)
             // = sb + 1, and b's distance to it is q - 1 - rb
-            sb = quot_rem(in_x ? p - d - 1 : 0, Rq, n, rb);
+            const uint64_t nb = in_x ? p - d - 1 : 0;   // < p, so sb <= k
+            // Partial quotients are mostly 1 or 2, and the lanes of a wave
+            // (pieces with nearly equal slopes) share their leading ones:
+            // when every lane's quotient is at most 2, subtractions replace
+            // the two divisions.
+            const uint64_t t1 = p - q, t2 = t1 - q;
+            const bool one = t1 < q;
+            if (wave_all(one || t2 < q)) {
+                k = one ? 1u : 2u;
+                rp = one ? t1 : t2;
+                sb = quot_small2(nb, q, rb);
+            } else {
+                const Recip Rq = recip(q);
+                k = quot_rem(p, Rq, n, rp);
+                sb = quot_rem(nb, Rq, n, rb);
+            }
             const uint64_t kiq = (uint64_t)k * iq;
             if (ip + iq + kiq >= n) break;
             const bool take = in_x && sb < k;
@@ -181,12 +215,21 @@ HR_HD void closest_left(uint64_t a, uint64_t b, uint32_t n, Near& r) {
             ip += (uint32_t)kiq;
             // ---- q > p: q-intervals (left ends >= iq) get points at p, 2p, ..
             ++steps;
-            const Recip Rp = recip(p);
             uint64_t rq;
-            k = quot_rem(q, Rp, n, rq);
             in_x = X >= iq;
             // b's interval is shorter than q, so sb = floor(d / p) <= k
-            sb = quot_rem(in_x ? d : 0, Rp, n, rb);
+            const uint64_t nq = in_x ? d : 0;
+            const uint64_t u1 = q - p, u2 = u1 - p;
+            const bool uone = u1 < p;
+            if (wave_all(uone || u2 < p)) {
+                k = uone ? 1u : 2u;
+                rq = uone ? u1 : u2;
+                sb = quot_small2(nq, p, rb);
+            } else {
+                const Recip Rp = recip(p);
+                k = quot_rem(q, Rp, n, rq);
+                sb = quot_rem(nq, Rp, n, rb);
+            }
             const uint64_t kip = (uint64_t)k * ip;
             if (ip + iq + kip >= n) {
                 q_step = true;

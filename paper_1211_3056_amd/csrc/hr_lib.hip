@@ -427,11 +427,18 @@ __global__ __launch_bounds__(64) void k_subtables(
             if ((uint32_t)w == (drop - 1) / 32) half.w[w] = 1u << ((drop - 1) % 32);
         hr::wadd(T, half);
     }
+    // limb w0 + i of T by selects over the constant indices: a run-time
+    // index into T would put the word in scratch memory
     const uint32_t w0 = drop / 32;
 #pragma unroll
     for (int w = 0; w < LU / 2; ++w) {
-        if ((uint32_t)w < lw)
-            dst[w] = ((uint64_t)T.w[w0 + 2 * w + 1] << 32) | T.w[w0 + 2 * w];
+        uint32_t lo = 0, hi = 0;
+#pragma unroll
+        for (int s = 0; s < LU; ++s) {
+            lo = ((uint32_t)s == w0 + 2 * w) ? T.w[s] : lo;
+            hi = ((uint32_t)s == w0 + 2 * w + 1) ? T.w[s] : hi;
+        }
+        if ((uint32_t)w < lw) dst[w] = ((uint64_t)hi << 32) | lo;
     }
 }
 
