@@ -24,9 +24,31 @@ HR_HD uint64_t mulhi64(uint64_t a, uint64_t b) {
 HR_HD uint64_t umin(uint64_t a, uint64_t b) { return a < b ? a : b; }
 
 // Correctly rounded binary64 value of x: both 32-bit halves convert
-// exactly, and one fused multiply-add rounds their sum once.
+// exactly, and one fused multiply-add rounds their sum once.  (On the
+// device the high half is converted in asm: written in C, the compiler
+// turns it back into a 64-bit conversion with an extra add.)
 HR_HD double u64_to_f64(uint64_t x) {
-    return __builtin_fma((double)(uint32_t)(x >> 32), 4294967296.0, (double)(uint32_t)x);
+    const uint32_t hi = (uint32_t)(x >> 32);
+#if defined(__HIP_DEVICE_COMPILE__)
+    double h;
+    asm("v_cvt_f64_u32 %0, %1" : "=v"(h) : "v"(hi));
+#else
+    const double h = (double)hi;
+#endif
+    return __builtin_fma(h, 4294967296.0, (double)(uint32_t)x);
+}
+
+// x truncated towards zero and clamped to [0, 2^32 - 1] (x not NaN).  The
+// device's conversion instruction clamps by itself; in C an out-of-range
+// conversion is undefined, hence the asm there.
+HR_HD uint32_t f64_to_u32_sat(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    uint32_t k;
+    asm("v_cvt_u32_f64 %0, %1" : "=v"(k) : "v"(x));
+    return k;
+#else
+    return (uint32_t)__builtin_fmin(__builtin_fmax(x, 0.0), 4294967295.0);
+#endif
 }
 
 // Reciprocal of a divisor, reused by every quotient with that divisor: on
@@ -55,22 +77,21 @@ HR_HD Recip recip(uint64_t den) {
 // num - q den when q < cap (unspecified when q = cap).
 // The binary64 estimate e of the quotient of the (rounded) operands is
 // within 2^-10 of the true quotient q + f (0 <= f < 1) whenever it is below
-// cap + 2.  Lowered by 2^-9, its floor is therefore q or q - 1, never q + 1:
-// k den <= num fits in 64 bits, and one compare of the remainder with den
-// (plus one subtraction) finishes the division.  Larger quotients saturate
-// at cap: callers only need to know that they reach cap.
+// cap + 2.  Lowered by 2^-9, its floor k is therefore q or q - 1, never
+// q + 1: k den <= num fits in 64 bits, and one compare of the remainder
+// with den (plus one subtraction) finishes the division.  A larger
+// estimate makes k (clamped to 2^32 - 1) at least cap, and so the result
+// cap: callers only need to know that the quotient reaches cap.
 HR_HD uint32_t quot_rem(uint64_t num, const Recip& R, uint32_t cap, uint64_t& rem) {
     const uint64_t den = R.den;
-    const double e = u64_to_f64(num) * R.r;
-    const bool big = e > (double)cap + 2.0;
-    const uint32_t k = (uint32_t)__builtin_fmin(__builtin_fmax(e - 0x1p-9, 0.0), 4294967295.0);
+    const uint32_t k = f64_to_u32_sat(__builtin_fma(u64_to_f64(num), R.r, -0x1p-9));
     const uint64_t kd = (uint64_t)k * (uint32_t)den +
                         ((uint64_t)(k * (uint32_t)(den >> 32)) << 32);   // k den, exact
     const uint64_t r0 = num - kd;      // in [0, 2 den)
     const bool under = r0 >= den;      // k = q - 1
     rem = under ? r0 - den : r0;
     const uint64_t kk = (uint64_t)k + under;
-    return (big || kk >= cap) ? cap : (uint32_t)kk;
+    return kk >= cap ? cap : (uint32_t)kk;
 }
 
 // floor(num / den) and the remainder for num < 3 den, by compares and

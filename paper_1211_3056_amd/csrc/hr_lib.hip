@@ -650,13 +650,9 @@ __device__ __forceinline__ bool top_rejects(const uint32_t* s_rows, const uint32
         hr::Word<4> V;
 #pragma unroll
         for (int w = 0; w < 4; ++w) V.w[w] = s_rows[src * row_stride(L, DEG) + L - 4 + w];
-        unsigned __int128 ck = 1;
         uint64_t M = DEG + 2;
-        static_for<1, DEG + 1>([&](auto J) {
+        auto top_row = [&](auto J, hr::Word<4>& r) {
             constexpr int j = decltype(J)::value;
-            ck = hr::binom_step(ck, k, j);
-            M += (uint64_t)(ck >> 64);
-            hr::Word<4> r;
             if constexpr (j < DEG) {
 #pragma unroll
                 for (int w = 0; w < 4; ++w)
@@ -664,10 +660,46 @@ __device__ __forceinline__ bool top_rejects(const uint32_t* s_rows, const uint32
             } else {
                 lds_word<4>(s_top + DEG * L + L - 4, r);
             }
-            uint32_t m[4];
-            hr::split128(ck, m);
-            hr::wmac128(V, r, m);
-        });
+        };
+        if (__ballot(k >= hr::binom64_limit(3)) == 0) {
+            // every lane's k < 2^21: C(k, j) for j <= 3 in 64 bits (two-limb
+            // multipliers), C(k, 4) = C(k, 3) (k - 3) / 4 from a 64 x 32-bit
+            // product (below 2^80, three limbs), higher ones in 128 bits;
+            // the limb counts are the same for every lane
+            uint64_t c = 1;
+            unsigned __int128 ck = 0;
+            static_for<1, DEG + 1>([&](auto J) {
+                constexpr int j = decltype(J)::value;
+                hr::Word<4> r;
+                top_row(J, r);
+                if constexpr (j <= 3) {
+                    c = hr::binom_step64(c, k, j);
+                    const uint32_t m[2] = {(uint32_t)c, (uint32_t)(c >> 32)};
+                    hr::wmac_n<4, 2>(V, r, m);
+                } else {
+                    if constexpr (j == 4)
+                        ck = ((unsigned __int128)c * (uint32_t)(k - 3)) >> 2;
+                    else
+                        ck = hr::binom_step(ck, k, j);
+                    M += (uint64_t)(ck >> 64);
+                    uint32_t m[4];
+                    hr::split128(ck, m);
+                    hr::wmac_n<4, (j == 4 ? 3 : 4)>(V, r, m);
+                }
+            });
+        } else {
+            unsigned __int128 ck = 1;
+            static_for<1, DEG + 1>([&](auto J) {
+                constexpr int j = decltype(J)::value;
+                ck = hr::binom_step(ck, k, j);
+                M += (uint64_t)(ck >> 64);
+                hr::Word<4> r;
+                top_row(J, r);
+                uint32_t m[4];
+                hr::split128(ck, m);
+                hr::wmac128(V, r, m);
+            });
+        }
         const uint64_t t = top64(V);
         const uint64_t hr_lo = thr[0], hr_hi = thr[1], rej_lo = thr[2], rej_hi = thr[3];
         const bool in_rej = t >= rej_lo && rej_hi >= M && t <= rej_hi - M;
