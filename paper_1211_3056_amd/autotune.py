@@ -20,6 +20,7 @@ fused pass.
 """
 from __future__ import annotations
 
+import functools
 import math
 from dataclasses import dataclass
 
@@ -64,17 +65,40 @@ def choose_degree(fname: str, X0: float, sub_len: int, s: int, uf, max_delta: in
     raise ValueError("no degree <= %d is accurate enough; use shorter sub-intervals" % max_delta)
 
 
+_DU_HINT: dict = {}
+
+
 def choose_upper_degree(fname: str, X0: float, count: int, s: int, delta: int = 1) -> int:
-    """Smallest degree >= delta of a range's upper polynomial whose Lagrange
-    remainder over the whole range is below eps 2^-12."""
+    """A degree >= delta of a range's upper polynomial whose Lagrange
+    remainder over the whole range is below eps 2^-12, with the one below it
+    too large (the smallest such degree, the remainder bound falling with
+    the degree on these ranges).  The last choice for the same function,
+    binade, length and eps is tried first, so that a stream of similar
+    jobs costs about two remainder bounds each."""
     uf = output_ulp_range(fname, X0, count)
     lim = mpf(2) ** (-s - MARGIN_BITS)
-    for Du in range(max(delta, 1), MAX_UPPER_DEGREE + 1):
-        if upper_error(fname, X0, count, Du, uf) <= lim:
-            return Du
-    raise ValueError("range too wide for one upper polynomial; split it")
+    lo = max(delta, 1)
+
+    def ok(Du):
+        return upper_error(fname, X0, count, Du, uf) <= lim
+
+    key = (fname, math.frexp(X0)[1], count, s, lo)
+    hint = _DU_HINT.get(key)
+    if hint is not None and ok(hint):
+        Du = hint
+        while Du > lo and ok(Du - 1):
+            Du -= 1
+    else:
+        Du = hint + 1 if hint is not None else lo
+        while Du <= MAX_UPPER_DEGREE and not ok(Du):
+            Du += 1
+        if Du > MAX_UPPER_DEGREE:
+            raise ValueError("range too wide for one upper polynomial; split it")
+    _DU_HINT[key] = Du
+    return Du
 
 
+@functools.lru_cache(maxsize=256)
 def choose_upper_width(Du: int, n_sub: int, N_max: int, tau_max: int, delta: int, s: int) -> int:
     """Narrowest upper-table width (>= 256 bits) that keeps the device's
     integer steps exact, (delta N)^Du < 2^Wu, and the share of the upper

@@ -27,6 +27,7 @@ Transcendental values come from mpmath at W + guard + 64 bits.
 """
 from __future__ import annotations
 
+import functools
 import math
 from dataclasses import dataclass
 from math import comb
@@ -182,8 +183,10 @@ class Prepared:
     uf: mpf
 
 
+@functools.lru_cache(maxsize=4096)
 def output_ulp_range(fname: str, X0: float, count: int) -> mpf:
-    """ulp of f on [X0, X0 + count h); f must stay in one binade there."""
+    """ulp of f on [X0, X0 + count h); f must stay in one binade there
+    (memoised: a job's preparation asks for it more than once)."""
     with mpmath.workprec(128):
         h = _ulp(X0)
         lo = _f(fname, mpf(X0))
@@ -373,7 +376,9 @@ def _kmat_cached(S: int, Du: int):
     if key not in _KCACHE:
         K = _k_matrices(S, Du)
         kmax = max(abs(v) for Kn in K for v in Kn.values())
-        _KCACHE[key] = (K, kmax.bit_length() + 96)
+        pairs = [(n, m) for n in range(Du + 1) for m in range(Du - n + 1)]
+        cols = [[(k, K[k][p]) for k in range(Du + 1) if K[k][p]] for p in pairs]
+        _KCACHE[key] = (K, kmax.bit_length() + 96, cols)
     return _KCACHE[key]
 
 
@@ -404,6 +409,7 @@ class UpperTable:
         return mpf(2) ** (-self.Wu) * sum(comb(T - 1, m) for m in range(self.Du - n + 1))
 
 
+@functools.lru_cache(maxsize=4096)
 def upper_error(fname: str, X0: float, count: int, Du: int, uf) -> mpf:
     """Lagrange remainder of the degree-Du Taylor polynomial at X0 over the
     whole range [X0, X0 + count h), in output ulps (closed-form bounds of
@@ -425,7 +431,7 @@ def upper_table(fname: str, X0: float, count: int, s: int, mode: str, S: int, Du
     if fname not in FUNCTIONS or Wu not in UPPER_WIDTHS or not 1 <= Du <= MAX_UPPER_DEGREE:
         raise ValueError("unsupported function, upper width or upper degree")
     uf = output_ulp_range(fname, X0, count) if uf is None else uf
-    K, G = _kmat_cached(S, Du)
+    K, G, cols = _kmat_cached(S, Du)
     pairs = [(n, m) for n in range(Du + 1) for m in range(Du - n + 1)]
     Lw = Wu // 64
     words = np.zeros((len(pairs), Lw), np.uint64)
@@ -437,8 +443,8 @@ def upper_table(fname: str, X0: float, count: int, s: int, mode: str, S: int, Du
         scale = mpf(2) ** (Wu + G)
         C = [int(mpmath.nint(cn * scale)) for cn in c]
     mask = (1 << Wu) - 1
-    for e, (n, m) in enumerate(pairs):
-        v = sum(C[k] * K[k][(n, m)] for k in range(Du + 1))
+    for e, col in enumerate(cols):
+        v = sum(C[k] * kv for k, kv in col)
         v = ((v + (1 << (G - 1))) >> G) & mask
         for li in range(Lw):
             words[e, li] = (v >> (64 * li)) & (M64 - 1)
@@ -525,6 +531,35 @@ def upper_windows_precise(U: UpperTable, N: int, tau: int, delta: int, W: int):
 _UP = 1.0 + 2.0 ** -40          # covers the rounding of the float sums below
 
 
+_WCONST: dict = {}
+
+
+def _window_consts(Du: int, Wu: int, n_sub: int, N: int, tau: int, d: int, W: int):
+    """The parts of upper_windows that do not depend on the function: the
+    binomial factors, the shift errors' kept entries and the rounding bound
+    (floats with the same outward margins), cached per job shape."""
+    key = (Du, Wu, n_sub, N, tau, d, W)
+    if key not in _WCONST:
+        T = n_sub
+        en = [float(mpf(2) ** (-Wu) * sum(comb(T - 1, m) for m in range(Du - n + 1))) * _UP
+              for n in range(Du + 1)]
+        cN = [float(comb(N - 1, j)) * _UP for j in range(Du + 1)]
+        cT = [float(comb(tau - 1, l)) * _UP for l in range(Du + 1)]
+        keptE = {}
+        for j in range(Du + 1):
+            for l in range(Du - j + 1):
+                if j + l <= d:
+                    keptE[(j, l)] = sum(en[n] * 2.0 ** l * float(comb(l * N, n - j)) * _UP
+                                        for n in range(j + l, Du + 1)) * _UP
+        e_shift = sum(v * cT[l] * cN[j] for (j, l), v in keptE.items()) * _UP
+        e_rw = float(round_bound(N, tau, d, W)) * _UP
+        kept_slack = [(sum(keptE[(j, l)] * cT[l] for l in range(d - j + 1)),
+                       2.0 ** (-W - 1) * sum(cT[l] for l in range(d - j + 1))) if j <= d
+                      else (0.0, 0.0) for j in range(Du + 1)]
+        _WCONST[key] = (cN, cT, e_shift, e_rw, kept_slack)
+    return _WCONST[key]
+
+
 def upper_windows(U: UpperTable, N: int, tau: int, delta: int, W: int):
     """The bounds of upper_windows_precise in binary64 arithmetic (a few
     hundred float operations instead of mpmath ones, for host preparation
@@ -537,6 +572,7 @@ def upper_windows(U: UpperTable, N: int, tau: int, delta: int, W: int):
     if not 1 <= d <= min(U.Du, 8):
         raise ValueError("degree must be between 1 and the upper degree")
     Du = U.Du
+    cN, cT, e_shift, e_rw, kept_slack = _window_consts(Du, U.Wu, U.n_sub, N, tau, d, W)
     c = [float(x) for x in U.coeffs]
     ca = [abs(x) * _UP for x in c]
     X = float(U.count + d * N + d)
@@ -544,20 +580,12 @@ def upper_windows(U: UpperTable, N: int, tau: int, delta: int, W: int):
     Xp = [X ** e * _UP for e in range(Du + 1)]
     Mx = [sum(ca[k] * fac[k] / fac[k - n] * Xp[k - n] for k in range(n, Du + 1)) * _UP
           for n in range(Du + 1)]
-    en = [float(U.shift_error(n)) * _UP for n in range(Du + 1)]
-    cN = [float(comb(N - 1, j)) * _UP for j in range(Du + 1)]
-    cT = [float(comb(tau - 1, l)) * _UP for l in range(Du + 1)]
-    drop, keptE = {}, {}
+    drop = {}
     for j in range(Du + 1):
         for l in range(Du - j + 1):
             if j + l > d:
                 drop[(j, l)] = float(N) ** l * Mx[j + l] * _UP
-            else:
-                keptE[(j, l)] = sum(en[n] * 2.0 ** l * float(comb(l * N, n - j)) * _UP
-                                    for n in range(j + l, Du + 1)) * _UP
     e_drop = sum(v * cT[l] * cN[j] for (j, l), v in drop.items()) * _UP
-    e_shift = sum(v * cT[l] * cN[j] for (j, l), v in keptE.items()) * _UP
-    e_rw = float(round_bound(N, tau, d, W)) * _UP
     mu = (float(U.e_approx) * _UP + e_drop + e_shift + e_rw) * _UP
     t_lo = t_hi = 0.0
     for j in range(2, d + 1):
@@ -570,8 +598,7 @@ def upper_windows(U: UpperTable, N: int, tau: int, delta: int, W: int):
             hi_j += max(term, 0.0)
             mag += abs(term)
         slack = (sum(drop[(j, l)] * cT[l] for l in range(d - j + 1, Du - j + 1))
-                 + sum(keptE[(j, l)] * cT[l] for l in range(d - j + 1))
-                 + 2.0 ** (-W - 1) * sum(cT[l] for l in range(d - j + 1))) * _UP
+                 + kept_slack[j][0] + kept_slack[j][1]) * _UP
         margin = mag * 2.0 ** -40 + slack
         t_lo += min(lo_j - margin, 0.0) * cN[j] * _UP
         t_hi += max(hi_j + margin, 0.0) * cN[j] * _UP
