@@ -208,23 +208,9 @@ __host__ __device__ constexpr int entry(int deg, int j, int l) {
     return j * (deg + 1) - j * (j - 1) / 2 + l;
 }
 
-// Multiplier limbs of C(x, 1..DEG) (c[m-1] = C(x, m)).  When every active
-// lane's x is small enough for 64-bit products, the binomials are built in
-// 64 bits (same values, no 128-bit multiplications).
+// Multiplier limbs of C(x, 1..DEG) (c[m-1] = C(x, m)).
 template <int DEG>
 __device__ __forceinline__ void binom_limbs(uint64_t x, uint32_t (*c)[4]) {
-    if (__ballot(x >= hr::binom64_limit(DEG)) == 0) {
-        uint64_t b = 1;
-#pragma unroll
-        for (int m = 0; m < DEG; ++m) {
-            b = hr::binom_step64(b, x, m + 1);
-            c[m][0] = (uint32_t)b;
-            c[m][1] = (uint32_t)(b >> 32);
-            c[m][2] = 0;
-            c[m][3] = 0;
-        }
-        return;
-    }
     unsigned __int128 b[DEG];
     hr::binoms128(x, DEG, b);
 #pragma unroll
