@@ -35,7 +35,7 @@ PEAK_HBM = 8.0e12                     # bytes/s
 # HBM bytes per launch measured by rocprofv3 (FETCH_SIZE x 1.997 and
 # WRITE_SIZE x 0.999, the factors a 1 GiB copy gives; summary under
 # profiles/), valid only for the kernel sources they were taken on.
-PROFILED_SOURCES = "137b37dfbd8e2309"      # sha256 prefix of hr_lib.hip + hr_core.h
+PROFILED_SOURCES = "c2a1dc83a8fa7078"      # sha256 prefix of hr_lib.hip + hr_core.h
 PROFILED_TRAFFIC = {"k_pipeline<8,4>": 4.99e6, "k_tabulate<8,4>": 69.15e6}
 
 
