@@ -131,11 +131,17 @@ class FusedStep:
         E = (spec.delta + 1) * (spec.delta + 2) // 2
         self.table = torch.empty(spec.n_sub * E * (spec.W // 64), dtype=torch.uint64, device=dev)
         self.RB = _lib.RESULT_BYTES
-        self.out = torch.empty(cap * self.RB, dtype=torch.uint8, device=dev)
-        self.counters = torch.zeros(9, dtype=torch.uint64, device=dev)   # count, stats[8]
-        self.count, self.stats = self.counters[:1], self.counters[1:]
-        self.count_h = torch.zeros(1, dtype=torch.uint64).pin_memory()
-        self.res_h = torch.zeros(cap * self.RB, dtype=torch.uint8).pin_memory()
+        # one device buffer: count, stats[8], padding to 96 bytes, then the
+        # result rows, so that a step copies its outputs back in one transfer
+        H = 12
+        self.H = H
+        self.dev = torch.zeros(H + cap * self.RB // 8, dtype=torch.uint64, device=dev)
+        self.counters = self.dev[:9]
+        self.count, self.stats = self.dev[:1], self.dev[1:9]
+        self.out = self.dev[H:].view(torch.uint8)
+        self.host = torch.zeros(H + cap * self.RB // 8, dtype=torch.uint64).pin_memory()
+        self.count_h = self.host[:1]
+        self.res_h = self.host[H:].view(torch.uint8)
         # rows fetched per step: every step searches the same batch, so the
         # last count (rounded up) bounds this one; rows beyond it are fetched
         # after the loop, inside the timed region
@@ -156,9 +162,8 @@ class FusedStep:
                          self.thr, self.out, self.cap, self.count, self.stats, st)
         if ev:
             ev[2].record(st)
-        self.count_h.copy_(self.count, non_blocking=True)
-        self.res_h[: self.fetch * self.RB].copy_(self.out[: self.fetch * self.RB],
-                                                 non_blocking=True)
+        n = self.H + self.fetch * self.RB // 8
+        self.host[:n].copy_(self.dev[:n], non_blocking=True)
 
     def settle(self):
         """After warm-up: fetch only the rows the last pass produced."""

@@ -170,14 +170,27 @@ HR_HD void closest_left(uint64_t a, uint64_t b, uint32_t n, Near& r) {
     uint32_t steps = 1;
     // First quotient: q is 1 (2^64), which does not fit; floor(2^64 / a) is
     // floor((2^64 - 1) / a) plus one when a divides 2^64.
-    const Recip Ra = recip(a);
-    uint64_t rem;
-    uint32_t k = quot_rem(~0ull, Ra, n, rem);
-    if (k < n && rem == a - 1) k += 1;
+    // When every lane's slope is above 1/3 (k <= 2), compares and
+    // subtractions give both quotients, as in the loop below.
+    uint32_t k;
+    uint32_t s0;                       // b's quotient by a (b sits in [0, 1))
+    const uint64_t a1 = 0 - a, a2 = a1 - a;   // 2^64 - a, 2^64 - 2a
+    const bool k_one = a1 < a;
+    if (wave_all(k_one || a2 < a)) {
+        k = k_one ? 1u : 2u;
+        uint64_t rb;
+        s0 = quot_small2(b, a, rb);   // b < 2^64 < 3a
+    } else {
+        const Recip Ra = recip(a);
+        uint64_t rem;
+        k = quot_rem(~0ull, Ra, n, rem);
+        if (k < n && rem == a - 1) k += 1;
+        uint64_t rb;
+        s0 = quot_rem(d, Ra, n, rb);
+    }
     {
         // b sits in the single interval [0, 1) whose left end has index 0
-        uint64_t rb;
-        const uint32_t s = (uint32_t)umin(umin(quot_rem(d, Ra, n, rb), k), n - 1);
+        const uint32_t s = (uint32_t)umin(umin(s0, k), n - 1);
         X = s;
         d -= (uint64_t)s * a;
     }
