@@ -66,6 +66,33 @@ def adversarial_instances(seed: int, n: int, max_N: int = 5000):
     return A, B, N, lo, D.astype(np.uint64)
 
 
+def wave_slopes(seed: int, n_waves: int, N: int = 1 << 16, spread_log2: int = 34):
+    """Instances in groups of 64 (one wave each) whose slopes are a base
+    slope plus lane times 2^spread_log2 (as for adjacent pieces of one
+    sub-interval), so that their leading partial quotients coincide; in
+    every other group one lane gets an unrelated slope.  Base slopes are
+    drawn in [1/3, 1), in (0, 1/3) and just above 1/2, b uniformly, N
+    fixed, the threshold 2^-14.  Returns (A, B, N[], D)."""
+    g = rng(seed)
+    n = 64 * n_waves
+    base = g.integers(0, 2 ** 64, n_waves, dtype=np.uint64, endpoint=False)
+    kind = g.integers(0, 3, n_waves)
+    third = np.uint64(0x5555555555555556)
+    with np.errstate(over="ignore"):
+        base = np.where(kind == 0, third + base % np.uint64(2 ** 64 - 0x5555555555555556 - 2 ** 41),
+                        np.where(kind == 1, np.uint64(1) + base % (third - np.uint64(2 ** 41)),
+                                 np.uint64(2 ** 63) + (base >> np.uint64(20))))
+        A = np.repeat(base, 64) + (np.tile(np.arange(64, dtype=np.uint64), n_waves)
+                                   << np.uint64(spread_log2))
+    odd = np.arange(n_waves) % 2 == 1
+    lane = g.integers(0, 64, n_waves)
+    rand = g.integers(1, 2 ** 64, n_waves, dtype=np.uint64, endpoint=False)
+    idx = (np.arange(n_waves) * 64 + lane)[odd]
+    A[idx] = rand[odd]
+    B = g.integers(0, 2 ** 64, n, dtype=np.uint64, endpoint=False)
+    return A, B, np.full(n, N, np.uint32), 1 << 50
+
+
 def random_tables(seed: int, n_sub: int, delta: int, W: int):
     """Uniformly random initial tables: uint64 (n_sub, E, W/64)."""
     g = rng(seed)

@@ -56,6 +56,22 @@ def test_adversarial_instances(seed):
     assert np.array_equal(h, rk)
 
 
+@pytest.mark.parametrize("seed", [31, 32])
+def test_wave_coherent_slopes(seed):
+    """Waves whose 64 slopes nearly agree, as for adjacent pieces (whole
+    waves take the walk's subtraction path while every quotient is at most
+    2), and every other wave with one unrelated slope (the wave takes the
+    division path at the steps that lane needs): every hit, bit for bit."""
+    A, B, N, D = synth.wave_slopes(seed, 64)
+    n = A.size
+    c, o, h, _ = _gpu(A, B, N, D)
+    rc, ro, rk = native.brute_hits_many(A, B, N, np.zeros(n, np.uint64), np.full(n, D, np.uint64))
+    assert np.array_equal(c, rc)
+    assert np.array_equal(o, ro)
+    assert np.array_equal(h, rk)
+    assert rk.size > 4 * n // 2         # about 4 hits per instance
+
+
 def test_grouped_windows_and_ragged_tail():
     g = synth.rng(5)
     n, group = 1000 + 37, 7            # ragged last group and last block
