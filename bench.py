@@ -276,6 +276,7 @@ def main():
     line["tabulation"] = bench_tabulation(spec, step.table, ctx, stream, args.steps)
     line["config1"] = bench_config1(ctx, stream, args.steps)
     line["config2"] = bench_config2(ctx, stream, args)
+    line["refinement"] = bench_refinement(spec, ctx, stream, res)
     line["filters"] = bench_filters(ctx, stream)
     line["cpu_simd"] = bench_cpu_simd(step, ctx, stream)
     if not args.no_plain:
@@ -556,6 +557,31 @@ def bench_cpu_simd(step, ctx, stream):
             "config1_s": t1, "config1_args_per_s": len(A1) * int(N1[0]) / t1,
             "config1_hits": int(len(h1)),
             "note": "degree-1 search only (tabulation and recheck not included)"}
+
+
+def bench_refinement(spec, ctx, stream, res_ref):
+    """The 2^40 slice with pieces split s ways from the start (N / s
+    arguments, tau s pieces per sub-interval; the paper's phase-2 split
+    applied to every piece): candidates fall about s^2-fold, the walks grow
+    s-fold.  Same HR cases as the headline step, compared here."""
+    import numpy as np
+    out = {"workload": "config 3 with pieces of N/s arguments"}
+    ref = np.sort(res_ref[res_ref["cls"] == 1], order=["sub", "piece", "k"])
+    ref_m = (ref["sub"].astype(np.int64) * spec.per_sub + ref["piece"].astype(np.int64) * spec.N
+             + ref["k"].astype(np.int64))
+    for sdiv in (2, 4):
+        sp = dataclasses.replace(spec, N=spec.N // sdiv, tau=spec.tau * sdiv)
+        step = FusedStep(sp, ctx, stream)
+        ms, ev_ms, res, st = timed_steps(step, 5, 2)
+        hr = res[res["cls"] == 1]
+        m = np.sort(hr["sub"].astype(np.int64) * sp.per_sub + hr["piece"].astype(np.int64) * sp.N
+                    + hr["k"].astype(np.int64))
+        out[f"s{sdiv}"] = {"N": sp.N, "ms_per_step": ms,
+                           "kernel_ms": sum(b for _, b in ev_ms) / len(ev_ms),
+                           "candidates": int(st[1]), "partial_quotients": int(st[3]),
+                           "hr_cases": int(len(hr)),
+                           "same_hr_as_headline": bool(np.array_equal(m, np.sort(ref_m)))}
+    return out
 
 
 def bench_hard_binade(args):
