@@ -356,6 +356,15 @@ def bench_stream(spec, ctx, stream, n_jobs=8):
         hr, _ = pipeline._finish(Pu, res["sub"], res["piece"], res["k"], res["cls"])
         return len(hr)
 
+    # one untimed job through both buffer sets first (a slice after the
+    # measured ones): pinned staging buffers and the launch path are warm
+    for i in range(2):
+        sp = dataclasses.replace(spec, X0=1.0 + (n_jobs + i) * 2.0 ** -12)
+        Du = autotune.choose_upper_degree(sp.fname, sp.X0, sp.count, sp.s, sp.delta)
+        Wu = autotune.choose_upper_width(Du, sp.n_sub, sp.N, sp.tau, sp.delta, sp.s)
+        Pw = pipeline.UpperPrepared(sp, Du, Wu)
+        launch(Pw, bufs[i])
+        finish(Pw, bufs[i])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     prep_s = 0.0

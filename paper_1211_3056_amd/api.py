@@ -27,6 +27,16 @@ def to_dev(x, dtype, device="cuda"):
     return torch.from_numpy(np.ascontiguousarray(np.asarray(x, dtype=np_dtype))).to(device)
 
 
+def to_dev_async(x, dtype, device="cuda"):
+    """Like to_dev, through pinned host memory and a copy queued on the
+    current stream: the host does not wait for work already queued there
+    (a copy from pageable memory would).  The pinned buffer stays reserved
+    until the copy has run."""
+    np_dtype = {torch.uint64: np.uint64, torch.uint32: np.uint32, torch.uint8: np.uint8}[dtype]
+    h = torch.from_numpy(np.ascontiguousarray(np.asarray(x, dtype=np_dtype))).pin_memory()
+    return h.to(device, non_blocking=True)
+
+
 def _u64_scalar(t: torch.Tensor) -> int:
     return int(t.cpu().numpy()[0])
 

@@ -90,9 +90,9 @@ def upload_upper(Pu: UpperPrepared, device="cuda"):
     """Upper table, and per-sub-interval window and threshold arrays (the
     shared values repeated), on the device."""
     n = Pu.spec.n_sub
-    upper = api.to_dev(Pu.U.words.reshape(-1), torch.uint64, device)
-    win = api.to_dev(Pu.win, torch.uint64, device).repeat(n)
-    thr = api.to_dev(Pu.thr, torch.uint64, device).repeat(n)
+    upper = api.to_dev_async(Pu.U.words.reshape(-1), torch.uint64, device)
+    win = api.to_dev_async(Pu.win, torch.uint64, device).repeat(n)
+    thr = api.to_dev_async(Pu.thr, torch.uint64, device).repeat(n)
     return upper, win, thr
 
 
