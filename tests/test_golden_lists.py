@@ -57,3 +57,23 @@ def test_config4_list():
         total += len(cases)
         expect += 2 * 2.0 ** -d["s"] * d["count"]
     assert abs(total - expect) < 4 * math.sqrt(expect)
+
+
+def test_config4_log_list():
+    """The log jobs of the batched workload: every sampled case is HR; the
+    count is not held to the 2 eps density (near 3 the values of log sit
+    close to a lattice mod 1), only to lie within a factor of it."""
+    got = golden_hr_lists("config4_log")
+    if got is None:
+        pytest.skip("hr_config4_log.txt not generated")
+    jobs = [d for d in synth.config4() if d["fname"] == "log"]
+    assert sorted(got) == [d["job_id"] for d in jobs]
+    total = expect = 0
+    for d in jobs:
+        cases = got[d["job_id"]]
+        assert len(cases) == len(set(cases)) and all(0 <= m < d["count"] for m in cases)
+        job = Job(d["fname"], d["X0"], d["count"], d["s"], d["mode"], 1 << 16, 1 << 12, 3, 128)
+        _check_cases(job, cases, sample=4)
+        total += len(cases)
+        expect += 2 * 2.0 ** -d["s"] * d["count"]
+    assert expect / 4 < total < 4 * expect

@@ -134,11 +134,12 @@ def test_graph_replays_match_eager():
 
 def test_full_batch_workload_full_lists():
     """The 16-job mix at full size (1.6e12 arguments) in the persistent launch
-    the benchmark times: the whole HR list of every exp, 2^x and sin job
-    equals the oracle's stored list (tests/golden/hr_config4.txt; the oracle
-    cuts the ranges its own way, the HR set does not depend on the cut).
-    For every function, log included, the last sub-interval of its first job
-    (a partial last piece) is recomputed by the oracle here as well."""
+    the benchmark times: the whole HR list of every job equals the oracle's
+    stored list (tests/golden/hr_config4.txt for the exp, 2^x and sin jobs,
+    hr_config4_log.txt for the log jobs; the oracle cuts the ranges its own
+    way, the HR set does not depend on the cut).  For every function the
+    last sub-interval of its first job (a partial last piece) is recomputed
+    by the oracle here as well."""
     from paper_1211_3056_amd import batch
     plan = batch.build_plan(_scaled_jobs())
     run = batch.Runner(batch.DevicePlan(plan))
@@ -160,6 +161,12 @@ def test_full_batch_workload_full_lists():
     assert sorted(ref) == sorted(pj.job.job_id for pj in listed)
     for pj in listed:
         assert hr[pj.job.job_id] == ref[pj.job.job_id], pj.job.job_id
+    ref_log = golden_hr_lists("config4_log")
+    assert ref_log is not None, "hr_config4_log.txt missing"
+    logs = [pj for pj in plan.jobs if pj.job.fname == "log"]
+    assert sorted(ref_log) == sorted(pj.job.job_id for pj in logs)
+    for pj in logs:
+        assert hr[pj.job.job_id] == ref_log[pj.job.job_id], pj.job.job_id
 
 
 def test_hard_binade_against_oracle():
