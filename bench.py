@@ -4,15 +4,16 @@ sub-intervals of 2^28 arguments, degree-4 tables at 256 bits, degree-1 pieces
 of N = 2^18).
 
 One step is one pass of the whole hot path over the slice with the range's
-upper table (a degree-7 polynomial at 320 bits, 1.4 KB) resident in HBM: the
+upper table (a degree-7 polynomial at 256 bits, 1.15 KB) resident in HBM: the
 4096 sub-interval tables made on the device, tabulation of the 2^22 pieces,
 degree-1 search of every piece, exact recheck of every candidate (the last
 three fused in one launch), and the result list copied back to the host.
 Beside it: the plain launch chain (tabulate -> search -> recheck) on the
 same tables, the tabulation stage alone against a plain fill of the same
 bytes, the plain search workload and the small pipeline, a stream of
-distinct jobs end to end (host preparation included), the batched mix and
-the serving loop.
+distinct jobs end to end (host preparation included), the slice with its
+pieces split 2 and 4 ways, the paper's lower-bound tests, the CPU SIMD
+search, the batched mix, the hard binade and the serving loop.
 
 Prints one JSON line.
 """
