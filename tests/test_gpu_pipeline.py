@@ -74,6 +74,26 @@ def test_config3_full_list():
         assert [m for m in got if lo <= m < hi] == ohr.pipeline(job, subs=[t])
 
 
+@pytest.mark.parametrize("split", [2, 4])
+def test_config3_refined_pieces_full_list(split):
+    """The same 2^40 arguments with every piece split `split` ways from the
+    start (pieces of N / split, the paper's phase-2 refinement applied to all
+    of them), tables made on the device from the upper polynomial: fewer
+    candidates, the same whole HR list as the oracle's stored one."""
+    import dataclasses
+
+    from paper_1211_3056_amd import pipeline
+    from paper_1211_3056_amd.prep import JobSpec
+    ref = golden_hr_lists("config3")
+    if ref is None:
+        pytest.skip("hr_config3.txt not generated")
+    base = JobSpec(**synth.CONFIG3)
+    spec = dataclasses.replace(base, N=base.N // split, tau=base.tau * split)
+    got, st = pipeline.search_job(spec, "upper")
+    assert st["pieces"] == (1 << 22) * split
+    assert got == ref[0]
+
+
 def test_paper_table3_full_list():
     """The paper's Table 3 workload: directed (53, 2^-32) HR cases of exp on
     [1, 1 + 2^-13], i.e. 2^39 + 1 binary64 arguments (its argument counts are
