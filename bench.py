@@ -33,11 +33,11 @@ METRIC = "binary64 args checked/sec (exp, 2^40 slice); batched vs plain speedup,
 PEAK_INT32_OPS = 256 * 64 * 2.4e9     # 256 CUs x 64 lanes x 2.4 GHz, one op/lane/clock
 PEAK_HBM = 8.0e12                     # bytes/s
 
-# HBM bytes per launch measured by rocprofv3 (FETCH_SIZE x 1.997 and
-# WRITE_SIZE x 0.999, the factors a 1 GiB copy gives; summary under
+# HBM bytes per launch measured by rocprofv3 (FETCH_SIZE x 2.000 and
+# WRITE_SIZE x 1.000, the factors a 1 GiB copy gives; summary under
 # profiles/), valid only for the kernel sources they were taken on.
-PROFILED_SOURCES = "ee893f29284cbcff"      # sha256 prefix of hr_lib.hip + hr_core.h
-PROFILED_TRAFFIC = {"k_pipeline<8,4>": 5.00e6, "k_tabulate<8,4>": 69.15e6}
+PROFILED_SOURCES = "a3f7d4b1130d2734"      # sha256 prefix of hr_lib.hip + hr_core.h
+PROFILED_TRAFFIC = {"k_pipeline<8,4>": 4.99e6, "k_tabulate<8,4>": 69.23e6}
 
 
 def profiled_traffic(kernel):

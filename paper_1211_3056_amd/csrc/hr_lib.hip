@@ -943,49 +943,154 @@ __device__ __forceinline__ void row_full_to_stride(hr::Word<L>* v) {
     });
 }
 
-// Lanes of a segment of H lanes take the pieces i0, i0 + H, .., of one
-// sub-interval: row 0 (giving b) and then row 1 (giving a) are each started
-// from the sub-interval's table at the lane's first piece (straightforward
-// shift, Sec. 5.2), turned into differences with step H, and advanced by
-// one tabulated-difference step per piece (Fig. 7).  At every step the H
-// lanes hold H consecutive pieces, so each store of a segment is one
-// contiguous, line-aligned run of 8 H bytes; one row at a time keeps the
-// kernel's registers low.
-template <int L, int DEG, int J, int H>
-__device__ __forceinline__ void tabulate_row(const uint64_t* __restrict__ T, uint64_t i0,
-                                             uint32_t cnt, uint64_t* __restrict__ dst) {
-    constexpr int LEN = DEG + 1 - J;
-    hr::Word<L> v[LEN];
-    {
-        uint32_t cb[DEG][4];
-        binom_limbs<DEG>(i0, cb);
-        row_start<L, DEG, J>(T, cb, v);
-    }
-    row_full_to_stride<L, LEN, H>(v);
-    for (uint32_t s = 0; s < cnt; ++s) {
-        dst[(uint64_t)H * s] = J == 0 ? top64(v[0]) : neg_top64(v[0]);
-        row_step<L, LEN>(v);
+__host__ __device__ constexpr int ilog2(uint64_t h) { return h <= 1 ? 0 : 1 + ilog2(h >> 1); }
+
+// acc = x 2^S mod 2^(32 L).
+template <int L, int S>
+__device__ __forceinline__ void wshl(hr::Word<L>& acc, const hr::Word<L>& x) {
+    constexpr int q = S / 32, r = S % 32;
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        const uint32_t hi = i - q >= 0 ? x.w[i - q] : 0u;
+        const uint32_t lo = i - q - 1 >= 0 ? x.w[i - q - 1] : 0u;
+        acc.w[i] = r == 0 ? hi : (hi << r) | (lo >> ((32 - r) & 31));
     }
 }
 
-// One wave = 64 / H segments; a segment is H lanes over H nu consecutive
-// pieces of one sub-interval (segs_per_sub segments per sub-interval).
-template <int L, int DEG, int H>
+// acc += x c mod 2^(32 L) for a 64-bit c; the high limb is skipped where
+// it is zero.
+template <int L>
+__device__ __forceinline__ void wmac64_skip(hr::Word<L>& acc, const hr::Word<L>& x, uint64_t c) {
+    const uint32_t m[2] = {(uint32_t)c, (uint32_t)(c >> 32)};
+    if (m[1] == 0) hr::wmac_n<L, 1>(acc, x, m);
+    else hr::wmac_n<L, 2>(acc, x, m);
+}
+
+// Row J's differences with step H at piece x, in one pass from the
+// sub-interval's step-1 differences at piece 0 (v in, v out):
+//   Delta_H^m r(x) = sum_{n >= m} c[m][n] Delta^n r(0),
+//   c[m][n] = sum_{k=m..n} A[m][k] C(x, n - k),
+// the straightforward shift to x (Sec. 5.2) composed with the change of
+// step (A = coefficients of (E^H - 1)^m in powers of Delta).  c[m][m] = H^m
+// is a shift.  Every c[m][n] is at most C(x + m H, n) (the coefficient of
+// Delta^n in E^(x + m H) dominates it term by term), so cb = C(x, 0..DEG)
+// in 64 bits and x + DEG H below binom64_limit(DEG) keep every c[m][n],
+// and every term of its sum, below 2^64.  Entry m reads entries >= m only,
+// so the pass runs in place in increasing m.
+template <int L, int DEG, int J, int H>
+__device__ __forceinline__ void row_start_stride(const uint64_t* __restrict__ T,
+                                                 const uint64_t* cb, hr::Word<L>* v) {
+    constexpr int LEN = DEG + 1 - J;
+    static_assert((H & (H - 1)) == 0, "step must be a power of two");
+#pragma unroll
+    for (int l = 0; l < LEN; ++l) load_word<L>(T + (size_t)entry(DEG, J, l) * (L / 2), v[l]);
+    static_for<0, LEN>([&](auto M) {
+        constexpr int m = decltype(M)::value;
+        hr::Word<L> acc;
+        wshl<L, m * ilog2(H)>(acc, v[m]);
+        static_for<m + 1, LEN>([&](auto N) {
+            constexpr int n = decltype(N)::value;
+            uint64_t c = 0;
+            static_for<m, n + 1>([&](auto K) {
+                constexpr int k = decltype(K)::value;
+                constexpr uint64_t a = stride_table<H>().a[m][k];
+                if constexpr (a != 0) c += a * cb[n - k];
+            });
+            wmac64_skip<L>(acc, v[n], c);
+        });
+        v[m] = acc;
+    });
+}
+
+// w = -w mod 2^(32 L).
+template <int L>
+__device__ __forceinline__ void wneg(hr::Word<L>& w) {
+    uint32_t c = 1;
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        uint32_t co;
+        w.w[i] = __builtin_addc(~w.w[i], 0u, c, &co);
+        c = co;
+    }
+}
+
+// Lanes of a segment of H lanes take the pieces i0, i0 + H, .., of one
+// sub-interval: row J (0 giving b, 1 giving a) is started from the
+// sub-interval's table at the lane's first piece (straightforward shift,
+// Sec. 5.2), turned into differences with step H, and advanced by one
+// tabulated-difference step per piece (Fig. 7).  At every step the H lanes
+// hold H consecutive pieces, so each store of a segment is one contiguous,
+// line-aligned run of 8 H bytes.  SMALL (every first piece i0 of the launch
+// has i0 + DEG H below binom64_limit(DEG)): the start is one composed pass
+// with 64-bit multipliers; otherwise the shift takes 128-bit binomials and
+// the step change follows as a second pass.
+template <int L, int DEG, int J, int H, bool SMALL>
+__device__ __forceinline__ void tabulate_row(const uint64_t* __restrict__ T, uint64_t i0,
+                                             uint32_t cnt, uint32_t nu,
+                                             uint64_t* __restrict__ dst) {
+    constexpr int LEN = DEG + 1 - J;
+    hr::Word<L> v[LEN];
+    if constexpr (SMALL) {
+        uint64_t cb[DEG + 1];
+        cb[0] = 1;
+#pragma unroll
+        for (int j = 1; j <= DEG; ++j) cb[j] = hr::binom_step64(cb[j - 1], i0, j);
+        row_start_stride<L, DEG, J, H>(T, cb, v);
+    } else {
+        uint32_t cb[DEG][4];
+        binom_limbs<DEG>(i0, cb);
+        row_start<L, DEG, J>(T, cb, v);
+        row_full_to_stride<L, LEN, H>(v);
+    }
+    if constexpr (J == 1) {
+        // a = floor(2^64 frac(-r_1)) is the top 64 bits of -r_1 mod 2^W, so
+        // the negated row is tabulated (the steps are linear).
+#pragma unroll
+        for (int l = 0; l < LEN; ++l) wneg<L>(v[l]);
+    }
+    if (hr::wave_all(cnt == nu) && (nu & 3) == 0) {
+        // every lane takes nu pieces: a uniform loop, four stores per
+        // address computation
+        uint64_t* p = dst;
+        for (uint32_t s = 0; s < nu; s += 4, p += 4 * H) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                p[H * u] = top64(v[0]);
+                row_step<L, LEN>(v);
+            }
+        }
+    } else {
+        for (uint32_t s = 0; s < cnt; ++s) {
+            dst[(uint64_t)H * s] = top64(v[0]);
+            row_step<L, LEN>(v);
+        }
+    }
+}
+
+// Workgroups 2w and 2w + 1 (one wave each) take the same 64 / H segments,
+// row 0 (b) and row 1 (a) respectively; a segment is H lanes over H nu
+// consecutive pieces of one sub-interval (segs_per_sub segments per
+// sub-interval).  One row per wave keeps a wave's registers to one
+// difference vector and doubles the waves that hide each other's stores,
+// at no extra packet starts.
+template <int L, int DEG, int H, bool SMALL>
 __global__ __launch_bounds__(64) void k_tabulate(const uint64_t* __restrict__ table,
                                                  uint32_t n_sub, uint32_t tau, uint32_t nu,
                                                  uint32_t segs_per_sub,
                                                  uint64_t* __restrict__ a_out,
                                                  uint64_t* __restrict__ b_out) {
     const int lane = threadIdx.x;
-    const uint64_t seg = (uint64_t)blockIdx.x * (64 / H) + lane / H;
+    const uint64_t seg = (uint64_t)(blockIdx.x >> 1) * (64 / H) + lane / H;
     const uint64_t sub = seg / segs_per_sub;
     if (sub >= n_sub) return;
     const uint64_t i0 = (seg % segs_per_sub) * H * nu + lane % H;
     if (i0 >= tau) return;
     const uint32_t cnt = (uint32_t)hr::umin(nu, (tau - i0 + H - 1) / H);
     const uint64_t* T = table + sub * n_entries(DEG) * (L / 2);
-    tabulate_row<L, DEG, 0, H>(T, i0, cnt, b_out + sub * tau + i0);
-    tabulate_row<L, DEG, 1, H>(T, i0, cnt, a_out + sub * tau + i0);
+    if ((blockIdx.x & 1) == 0)
+        tabulate_row<L, DEG, 0, H, SMALL>(T, i0, cnt, nu, b_out + sub * tau + i0);
+    else
+        tabulate_row<L, DEG, 1, H, SMALL>(T, i0, cnt, nu, a_out + sub * tau + i0);
 }
 
 // Statistics are summed per wave, then added into one of kStatSlots
@@ -1325,14 +1430,14 @@ bool valid_poly(uint32_t degree, uint32_t width_bits) {
 // hr_tabulate's segments: H lanes (32) over H nu pieces, nu up to 32 (long
 // enough to amortise the packet start, i.e. the straightforward shift and
 // the step conversion), lowered while the grid would have fewer than 8
-// waves per CU.
+// waves per CU (two waves per pair of segments, one per row).
 constexpr uint32_t kTabLanes = 32;
 constexpr uint32_t kTabMaxNu = 32;
 uint32_t pick_nu_tab(uint64_t n_sub, uint32_t tau) {
     uint32_t nu = kTabMaxNu;
     auto waves = [&](uint32_t v) {
         return n_sub * ((tau + (uint64_t)kTabLanes * v - 1) / ((uint64_t)kTabLanes * v)) /
-               (64 / kTabLanes);
+               (64 / kTabLanes) * 2;
     };
     while (nu > 1 && waves(nu) < 256ull * 8) nu >>= 1;
     return nu;
@@ -1507,11 +1612,18 @@ hr_status hr_tabulate(hr_ctx* ctx, const uint64_t* table, uint32_t n_sub, uint32
     const uint32_t nu = pick_nu_tab(n_sub, tau);
     const uint64_t sps = (tau + (uint64_t)kTabLanes * nu - 1) / ((uint64_t)kTabLanes * nu);
     const uint64_t segs_per_wave = 64 / kTabLanes;
-    const uint64_t blocks = ((uint64_t)n_sub * sps + segs_per_wave - 1) / segs_per_wave;
+    const uint64_t blocks = 2 * (((uint64_t)n_sub * sps + segs_per_wave - 1) / segs_per_wave);
     if (blocks > 0xffffffffull || sps > 0xffffffffull) return HR_EINVAL;
-    HR_DISPATCH(width_bits, degree,
-                (k_tabulate<L_, D_, kTabLanes><<<dim3((uint32_t)blocks), dim3(64), 0, st>>>(
-                    table, n_sub, tau, nu, (uint32_t)sps, a_out, b_out)));
+    // composed 64-bit start when every first piece (< tau) stays below the limit
+    const bool small = (uint64_t)tau - 1 + (uint64_t)degree * kTabLanes < hr::binom64_limit((int)degree);
+    if (small)
+        HR_DISPATCH(width_bits, degree,
+                    (k_tabulate<L_, D_, kTabLanes, true><<<dim3((uint32_t)blocks), dim3(64), 0, st>>>(
+                        table, n_sub, tau, nu, (uint32_t)sps, a_out, b_out)));
+    else
+        HR_DISPATCH(width_bits, degree,
+                    (k_tabulate<L_, D_, kTabLanes, false><<<dim3((uint32_t)blocks), dim3(64), 0, st>>>(
+                        table, n_sub, tau, nu, (uint32_t)sps, a_out, b_out)));
     return launched();
 }
 

@@ -43,6 +43,23 @@ def test_tabulate_random_tables(W, delta, tau):
     assert a.tolist() == ra and b.tolist() == rb
 
 
+@pytest.mark.parametrize("W,delta,tau", [(256, 4, 66000), (192, 5, 4500), (128, 6, 1500),
+                                         (256, 6, 700)])
+def test_tabulate_start_paths(W, delta, tau):
+    """Both packet starts: lanes whose first piece i0 has i0 + 32 delta below
+    the 64-bit binomial limit of delta (2^16, 2^12, 2^10) take the composed
+    shift and step change with 64-bit multipliers, later ones the 128-bit
+    shift and a second pass; a sub-interval of tau pieces crosses the limit
+    (tau = 700 at degree 6 stays just below it)."""
+    from paper_1211_3056_amd import api
+    n_sub = 2
+    tabs = synth.random_tables(7 * W + delta, n_sub, delta, W)
+    a, b = api.tabulate(api.to_dev(tabs.reshape(-1), torch.uint64), n_sub, delta, tau, W)
+    a, b = a.cpu().numpy(), b.cpu().numpy()
+    ra, rb = otab.tabulate(_words(tabs, delta), delta, tau, W)
+    assert a.tolist() == ra and b.tolist() == rb
+
+
 def test_tabulate_exp_tables_from_oracle():
     """Tables of exp written by the oracle (degree 4, 256 bits, tau = 1024)."""
     from paper_1211_3056_amd import api
