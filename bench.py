@@ -149,22 +149,25 @@ class FusedStep:
         self.fetch = cap
 
     def __call__(self, ev=None):
-        import torch  # noqa: F401
+        import torch
 
         from paper_1211_3056_amd import _lib, pipeline
         sp, st = self.spec, self.stream
-        self.counters.zero_()
-        if ev:
-            ev[0].record(st)
-        pipeline.make_tables(self.Pu, self.upper, ctx=self.ctx, stream=st, out=self.table)
-        if ev:
-            ev[1].record(st)
-        _lib.hr_pipeline(self.ctx, self.table, sp.n_sub, sp.delta, sp.tau, sp.W, sp.N, self.win,
-                         self.thr, self.out, self.cap, self.count, self.stats, st)
-        if ev:
-            ev[2].record(st)
-        n = self.H + self.fetch * self.RB // 8
-        self.host[:n].copy_(self.dev[:n], non_blocking=True)
+        # the clearing and the copy back go on the step's stream, ordered
+        # with its launches
+        with torch.cuda.stream(st):
+            self.counters.zero_()
+            if ev:
+                ev[0].record(st)
+            pipeline.make_tables(self.Pu, self.upper, ctx=self.ctx, stream=st, out=self.table)
+            if ev:
+                ev[1].record(st)
+            _lib.hr_pipeline(self.ctx, self.table, sp.n_sub, sp.delta, sp.tau, sp.W, sp.N,
+                             self.win, self.thr, self.out, self.cap, self.count, self.stats, st)
+            if ev:
+                ev[2].record(st)
+            n = self.H + self.fetch * self.RB // 8
+            self.host[:n].copy_(self.dev[:n], non_blocking=True)
 
     def settle(self):
         """After warm-up: fetch only the rows the last pass produced."""
@@ -339,15 +342,16 @@ def bench_stream(spec, ctx, stream, n_jobs=8):
                      "done": torch.cuda.Event()})
 
     def launch(Pu, b):
-        upper, win, thr = pipeline.upload_upper(Pu)
-        pipeline.make_tables(Pu, upper, ctx=ctx, stream=stream, out=b["table"])
-        b["count"].zero_()
-        sp = Pu.spec
-        _lib.hr_pipeline(ctx, b["table"], sp.n_sub, sp.delta, sp.tau, sp.W, sp.N, win, thr,
-                         b["out"], cap, b["count"], None, stream)
-        b["count_h"].copy_(b["count"], non_blocking=True)
-        b["res_h"].copy_(b["out"], non_blocking=True)
-        b["done"].record(stream)
+        with torch.cuda.stream(stream):
+            upper, win, thr = pipeline.upload_upper(Pu)
+            pipeline.make_tables(Pu, upper, ctx=ctx, stream=stream, out=b["table"])
+            b["count"].zero_()
+            sp = Pu.spec
+            _lib.hr_pipeline(ctx, b["table"], sp.n_sub, sp.delta, sp.tau, sp.W, sp.N, win, thr,
+                             b["out"], cap, b["count"], None, stream)
+            b["count_h"].copy_(b["count"], non_blocking=True)
+            b["res_h"].copy_(b["out"], non_blocking=True)
+            b["done"].record(stream)
 
     def finish(Pu, b):
         b["done"].synchronize()
