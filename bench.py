@@ -13,7 +13,8 @@ same tables, the tabulation stage alone against a plain fill of the same
 bytes, the plain search workload and the small pipeline, a stream of
 distinct jobs end to end (host preparation included), the slice with its
 pieces split 2 and 4 ways, the paper's lower-bound tests, the CPU SIMD
-search, the batched mix, the hard binade and the serving loop.
+search, the batched mix (with its kernel's algorithmic VALU fraction), the
+hard binade and the serving loop.
 
 Prints one JSON line.
 """
@@ -25,6 +26,7 @@ import json
 import os
 import sys
 import time
+import types
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -843,6 +845,28 @@ def bench_batch(args):
         res_b = run.batched()
         tb.append(time.perf_counter() - t0)
     st = run.stats_dict()
+    # device time of the batched launch alone (counter fills and one
+    # persistent launch per (W, delta) group), by events on the stream
+    dev_ms = []
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        run.batched(sync=False)
+        e1.record()
+        torch.cuda.synchronize()
+        dev_ms.append(e0.elapsed_time(e1))
+    dev_med = sorted(dev_ms)[len(dev_ms) // 2]
+    groups = sorted({(pj.W, pj.delta) for pj in plan.jobs})
+    roof = None
+    if len(groups) == 1:
+        # the headline kernel's ops model, with this plan's width and degree
+        W, d = groups[0]
+        ops = ops_model(types.SimpleNamespace(W=W, delta=d), st["pieces"], st["candidates"],
+                        st["partial_quotients"], st["full_evaluations"])
+        roof = {"bound": "alu", "kernel": f"k_items<{W // 32},{d},true>",
+                "device_ms": dev_med, "achieved": ops / (dev_med / 1000) / 1e12,
+                "peak": PEAK_INT32_OPS / 1e12, "unit": "Tops/s (int32 VALU, algorithmic)",
+                "frac": ops / (dev_med / 1000) / PEAK_INT32_OPS}
     graph = run.capture()
     graph.replay()
     graph.results()
@@ -876,7 +900,7 @@ def bench_batch(args):
             "graph_ms": min(tg) * 1000, "graph_speedup": p_s / min(tg),
             "graph_identical": bool(same_graph),
             "hr_cases": sum(len(v) for v in hr.values()), "candidates": st["candidates"],
-            "nmdm_wave64": st["nmdm"],
+            "nmdm_wave64": st["nmdm"], "roofline": roof,
             "host_prep_s": plan.prep_s, "device_tables_ms": dp.tables_ms,
             "upper_degrees": sorted({r[2] for tp, _ in plan.tables for r in tp.ranges})}
 
