@@ -38,8 +38,8 @@ PEAK_HBM = 8.0e12                     # bytes/s
 # HBM bytes per launch measured by rocprofv3 (FETCH_SIZE x 2.000 and
 # WRITE_SIZE x 1.000, the factors a 1 GiB copy gives; summary under
 # profiles/), valid only for the kernel sources they were taken on.
-PROFILED_SOURCES = "a3f7d4b1130d2734"      # sha256 prefix of hr_lib.hip + hr_core.h
-PROFILED_TRAFFIC = {"k_pipeline<8,4>": 4.99e6, "k_tabulate<8,4>": 69.23e6}
+PROFILED_SOURCES = "40ed1c3e663831aa"      # sha256 prefix of hr_lib.hip + hr_core.h
+PROFILED_TRAFFIC = {"k_pipeline<8,4>": 5.01e6, "k_tabulate<8,4>": 68.96e6}
 
 
 def profiled_traffic(kernel):

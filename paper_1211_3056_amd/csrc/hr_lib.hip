@@ -1067,12 +1067,13 @@ __device__ __forceinline__ void tabulate_row(const uint64_t* __restrict__ T, uin
     }
 }
 
-// Workgroups 2w and 2w + 1 (one wave each) take the same 64 / H segments,
-// row 0 (b) and row 1 (a) respectively; a segment is H lanes over H nu
-// consecutive pieces of one sub-interval (segs_per_sub segments per
-// sub-interval).  One row per wave keeps a wave's registers to one
-// difference vector and doubles the waves that hide each other's stores,
-// at no extra packet starts.
+// Workgroup w of the first half of the grid (one wave each) and workgroup
+// w of the second half take the same 64 / H segments, row 0 (b) and row 1
+// (a) respectively; a segment is H lanes over H nu consecutive pieces of
+// one sub-interval (segs_per_sub segments per sub-interval).  One row per
+// wave keeps a wave's registers to one difference vector and doubles the
+// waves that hide each other's stores, at no extra packet starts; the
+// longer row-0 waves are dispatched first.
 template <int L, int DEG, int H, bool SMALL>
 __global__ __launch_bounds__(64) void k_tabulate(const uint64_t* __restrict__ table,
                                                  uint32_t n_sub, uint32_t tau, uint32_t nu,
@@ -1080,14 +1081,16 @@ __global__ __launch_bounds__(64) void k_tabulate(const uint64_t* __restrict__ ta
                                                  uint64_t* __restrict__ a_out,
                                                  uint64_t* __restrict__ b_out) {
     const int lane = threadIdx.x;
-    const uint64_t seg = (uint64_t)(blockIdx.x >> 1) * (64 / H) + lane / H;
+    const uint32_t half = gridDim.x / 2;   // the grid is even
+    const uint32_t row = blockIdx.x >= half;
+    const uint64_t seg = (uint64_t)(blockIdx.x - row * half) * (64 / H) + lane / H;
     const uint64_t sub = seg / segs_per_sub;
     if (sub >= n_sub) return;
     const uint64_t i0 = (seg % segs_per_sub) * H * nu + lane % H;
     if (i0 >= tau) return;
     const uint32_t cnt = (uint32_t)hr::umin(nu, (tau - i0 + H - 1) / H);
     const uint64_t* T = table + sub * n_entries(DEG) * (L / 2);
-    if ((blockIdx.x & 1) == 0)
+    if (row == 0)
         tabulate_row<L, DEG, 0, H, SMALL>(T, i0, cnt, nu, b_out + sub * tau + i0);
     else
         tabulate_row<L, DEG, 1, H, SMALL>(T, i0, cnt, nu, a_out + sub * tau + i0);
